@@ -1,0 +1,192 @@
+/*
+ * tssvd.h — C ABI of the MI355X (gfx950) tall-skinny and randomized low-rank SVD library.
+ *
+ * Method: Li, Kluger, Tygert, "Randomized algorithms for distributed computation of
+ * principal component analysis and singular value decomposition".
+ *   - tsqr / tssvd      : Algorithms 1 and 2 (Section 2): Householder TSQR reduced up a
+ *                         binary tree, SVD of the small triangular factor, U = Q U~,
+ *                         optional second orthonormalization.
+ *   - lowrank_svd       : Algorithm 7 (Section 3) = Algorithm 5 (randomized subspace
+ *                         iteration) feeding Algorithm 6 (direct SVD of B = Q^* A).
+ *   - lowrank_svd_backward : vector-Jacobian product of lowrank_svd with the sketch held
+ *                         fixed (not in the paper; the reverse mode of the same forward).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are row-major.  "ld" arguments are row strides in elements (ld >= columns).
+ *   - Every matrix/vector pointer is a DEVICE pointer owned by the caller.  The library
+ *     never allocates device or host memory and never synchronizes the stream: all work
+ *     is enqueued on `stream` (a hipStream_t; NULL = the legacy default stream).
+ *   - Scratch memory is the caller's `work` buffer (device, 256-byte aligned), sized by
+ *     the matching *_workspace_bytes query.  Its contents are undefined on return.
+ *   - Inputs A may be float64 or float32 (a_dtype).  Outputs U, S, V are float64.
+ *   - Return value: a tssvd_status for errors detectable on the host (checked before
+ *     any work is enqueued; nothing is enqueued on error).  Numerical conditions found
+ *     on the device are written to the optional device record `info`.
+ *   - Singular values are descending and non-negative.  Sign convention: each pair
+ *     (u_j, v_j) is oriented so that w^T v_j >= 0 with w_i = frac((i+1) g) - 1/2,
+ *     g = (sqrt(5)-1)/2, i = 0..n-1.  Triplets past the numerical rank (discard rule,
+ *     working_precision > 0) have sigma = 0 and zero columns in U and V.
+ *   - Results are bitwise reproducible for identical inputs, options and sizes (fixed
+ *     reduction orders, no floating-point atomics).
+ *   - Calls that share a `work` buffer must be ordered on one stream.
+ */
+#ifndef TSSVD_H
+#define TSSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Largest column count handled by tssvd and largest sketch width l for lowrank_svd.
+ * The small SVD keeps both n x n factors in the 160 KB local data share of one CU. */
+#define TSSVD_N_MAX 100
+/* Largest column count handled by tsqr alone. */
+#define TSSVD_TSQR_N_MAX 128
+
+typedef enum {
+  TSSVD_OK = 0,
+  TSSVD_E_INVALID_ARG = 1,   /* null pointer, bad size, ld too small, k > l, ...        */
+  TSSVD_E_WORKSPACE = 2,     /* work == NULL or work_bytes below the query's answer     */
+  TSSVD_E_HIP = 3,           /* a HIP launch failed                                     */
+  TSSVD_E_UNSUPPORTED = 4    /* size or option outside what this build implements      */
+} tssvd_status;
+
+typedef enum { TSSVD_F64 = 0, TSSVD_F32 = 1 } tssvd_dtype;
+
+typedef enum {
+  TSSVD_PREC_FP64 = 0,       /* every product and factorization in float64              */
+  TSSVD_PREC_MIXED = 1       /* lowrank_svd: power-iteration products in bfloat16 with
+                                float32 accumulation, final sketch and B products with
+                                float32 inputs and accumulation; TSQR, small SVD and the
+                                second orthonormalization in float64.  Requires a_dtype
+                                == TSSVD_F32.  tssvd: A is read as stored, all arithmetic
+                                float64.                                                */
+} tssvd_prec;
+
+typedef enum {
+  TSSVD_ORTHO_AUTO = 0,      /* measure ||U^T U - I||_F and run the second
+                                orthonormalization only if it exceeds reorth_tol       */
+  TSSVD_ORTHO_ONCE = 1,      /* Algorithm 1: one orthonormalization                     */
+  TSSVD_ORTHO_TWICE = 2      /* Algorithm 2: always orthonormalize twice                */
+} tssvd_ortho;
+
+typedef struct {
+  int32_t prec;              /* tssvd_prec                                               */
+  int32_t ortho;             /* tssvd_ortho (tssvd, and the last step of Algorithm 5)    */
+  double working_precision;  /* discard rule of Algorithms 1-2: rows of R with
+                                |R_jj| < wp |R_11| are dropped; <= 0 disables (default)  */
+  double reorth_tol;         /* TSSVD_ORTHO_AUTO threshold (default 1e-13)               */
+  int32_t max_jacobi_sweeps; /* cap on one-sided Jacobi sweeps in the small SVD (30)     */
+  int32_t reserved;
+  uint64_t seed;             /* Philox4x32-10 key used when lowrank_svd gets Omega==NULL */
+} tssvd_opts;
+
+/* Device-side record written (when non-NULL) at the end of every call. */
+typedef struct {
+  int32_t numstat;           /* bit 0: non-finite value met; bit 1: Jacobi sweep cap hit */
+  int32_t rank;              /* number of kept singular triplets                          */
+  int32_t sweeps;            /* Jacobi sweeps used by the last small SVD                  */
+  int32_t reorth;            /* 1 if a second orthonormalization pass ran                 */
+  double ortho;              /* ||Q^T Q - I||_F of the orthonormal factor before the
+                                conditional second pass; -1 when not measured            */
+} tssvd_info;
+
+void tssvd_default_opts(tssvd_opts* opts);
+const char* tssvd_status_string(int status);
+/* Library version as major*10000 + minor*100 + patch. */
+int tssvd_version(void);
+
+/* ---------------------------------------------------------------------------------------
+ * tsqr — Algorithm 1 step 2: A = Q R for a tall m x n matrix (m >= n, 1 <= n <= 128).
+ * Row blocks of A are reduced by structured Householder QR, the per-block R factors are
+ * merged pairwise up a fixed binary tree, and Q is formed explicitly by applying the
+ * stored reflectors to [I; 0] when Q != NULL.
+ *   A   : m x n, a_dtype, stride lda           (read)
+ *   Q   : m x n float64, stride ldq, or NULL    (written)
+ *   R   : n x n float64 upper triangular, stride ldr (written; strict lower part zeroed)
+ * The diagonal of R may be negative (Householder convention beta = -sign(alpha) ||x||).
+ * ------------------------------------------------------------------------------------- */
+int tsqr_workspace_bytes(int64_t m, int64_t n, int32_t a_dtype, size_t* bytes);
+int tsqr(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
+         double* Q, int64_t ldq, double* R, int64_t ldr,
+         void* work, size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * tssvd — thin SVD of a tall-skinny A (Algorithms 1 and 2): A = U diag(S) V^T.
+ *   A : m x n (m >= n, 1 <= n <= TSSVD_N_MAX), a_dtype, stride lda   (read)
+ *   U : m x n float64, stride ldu                                     (written)
+ *   S : n float64                                                     (written)
+ *   V : n x n float64, stride ldv                                     (written)
+ *   info : optional device tssvd_info                                 (written)
+ * opts == NULL means tssvd_default_opts.
+ * ------------------------------------------------------------------------------------- */
+int tssvd_workspace_bytes(int64_t m, int64_t n, int32_t a_dtype, const tssvd_opts* opts,
+                          size_t* bytes);
+int tssvd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
+          double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+          tssvd_info* info, void* work, size_t work_bytes, const tssvd_opts* opts,
+          void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * lowrank_svd — rank-k approximation A ~ U diag(S) V^T by Algorithm 7 with sketch width
+ * l and q power iterations (the paper's i): 2q+2 passes over A.
+ *   A     : m x n, a_dtype, stride lda.  Requires 0 < k <= l < min(m, n), l <= TSSVD_N_MAX,
+ *           q >= 0, and the sketched dimension n >= l.
+ *   Omega : n x l float64 row-major (stride l) Gaussian sketch, or NULL to draw it on the
+ *           device with Philox4x32-10 keyed by opts->seed (layout: entries in row-major
+ *           order, four per counter value t, counter (t mod 2^32, t div 2^32, 0, 0), key
+ *           (seed mod 2^32, seed div 2^32), Box-Muller on (u0,u1), (u2,u3) with
+ *           u = (x + 1/2) 2^-32).
+ *   U : m x k float64 (ldu), S : k float64, V : n x k float64 (ldv)     (written)
+ * ------------------------------------------------------------------------------------- */
+int lowrank_svd_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t l, int64_t q,
+                                int32_t a_dtype, const tssvd_opts* opts, size_t* bytes);
+int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
+                int64_t k, int64_t l, int64_t q, const double* Omega,
+                double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+                tssvd_info* info, void* work, size_t work_bytes, const tssvd_opts* opts,
+                void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * lowrank_svd_backward — dL/dA for a scalar loss L(U, S, V) of lowrank_svd's outputs,
+ * given the cotangents gU = dL/dU (m x k), gS = dL/dS (k), gV = dL/dV (n x k); any of the
+ * three may be NULL (zero).  The derivative is that of the implemented forward map with
+ * Omega held fixed: the forward is recomputed from (A, Omega) inside the call, so U, S, V
+ * must be the outputs of lowrank_svd on the same A, Omega, k, l, q and options.
+ *   gA : m x n, a_dtype, stride ldga (written)
+ * Requires opts->prec == TSSVD_PREC_FP64 and working_precision <= 0.
+ * ------------------------------------------------------------------------------------- */
+int lowrank_svd_backward_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t l,
+                                         int64_t q, int32_t a_dtype, const tssvd_opts* opts,
+                                         size_t* bytes);
+int lowrank_svd_backward(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
+                         int64_t k, int64_t l, int64_t q, const double* Omega,
+                         const double* U, int64_t ldu, const double* S, const double* V,
+                         int64_t ldv, const double* gU, const double* gS, const double* gV,
+                         void* gA, int64_t ldga, tssvd_info* info, void* work,
+                         size_t work_bytes, const tssvd_opts* opts, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Measurement support.  While enabled, HIP events are recorded on the call's stream right
+ * before and after every launch of the kernels that stream A (one kind per kernel family);
+ * tssvd_profile_read waits for the recorded events and returns the summed durations.
+ * Disabled (the default) it costs nothing.  Event objects are host-side HIP resources,
+ * created on first use and reused; no device memory is allocated.
+ * ------------------------------------------------------------------------------------- */
+enum {
+  TSSVD_PROF_AX = 0,           /* Y = A X passes over A                                   */
+  TSSVD_PROF_ATQ = 1,          /* Z = A^T Q passes over A (main kernel, before the reduce) */
+  TSSVD_PROF_LEAF_FACTOR = 2,  /* TSQR leaf factorization (reads the tall matrix)         */
+  TSSVD_PROF_LEAF_APPLY = 3,   /* TSQR leaf application (writes the tall factor)          */
+  TSSVD_PROF_KINDS = 4
+};
+int tssvd_profile_enable(int on);      /* on != 0: start recording (counters reset)      */
+int tssvd_profile_read(int kind, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSSVD_H */

@@ -1,0 +1,405 @@
+// C ABI: argument validation, workspace planning and the stream-ordered launch sequences
+// of tsqr, tssvd (Algorithms 1-2) and lowrank_svd (Algorithm 7).  No allocation, no
+// host synchronization: every step is enqueued on the caller's stream.
+#include <math.h>
+#include <string.h>
+
+#include "common.h"
+#include "internal.h"
+
+using namespace tsv;
+
+namespace {
+
+constexpr int VERSION = 100;  // 0.1.0
+
+bool bad_dtype(int32_t d) { return d != TSSVD_F64 && d != TSSVD_F32; }
+
+tssvd_opts resolve(const tssvd_opts* o) {
+  tssvd_opts r;
+  tssvd_default_opts(&r);
+  if (o) r = *o;
+  if (r.max_jacobi_sweeps <= 0) r.max_jacobi_sweeps = 30;
+  if (!(r.reorth_tol > 0.0)) r.reorth_tol = 1e-13;
+  return r;
+}
+
+int check_opts(const tssvd_opts& o) {
+  if (o.prec != TSSVD_PREC_FP64 && o.prec != TSSVD_PREC_MIXED) return TSSVD_E_INVALID_ARG;
+  if (o.ortho < TSSVD_ORTHO_AUTO || o.ortho > TSSVD_ORTHO_TWICE) return TSSVD_E_INVALID_ARG;
+  if (!isfinite(o.working_precision)) return TSSVD_E_INVALID_ARG;
+  return TSSVD_OK;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? TSSVD_OK : TSSVD_E_HIP; }
+
+#define TRY(expr)                               \
+  do {                                          \
+    hipError_t _e = (expr);                     \
+    if (_e != hipSuccess) return TSSVD_E_HIP;   \
+  } while (0)
+
+// ---------------------------------------------------------------- orthonormality gate
+// ortho = ||Q^T Q - I||_F (an upper bound of the spectral norm); gate = 1 when the
+// second orthonormalization must run (always for TWICE, ortho > tol for AUTO).
+__global__ void k_ortho_gate(const double* __restrict__ G, int k, int mode, double tol,
+                             double* __restrict__ ortho_out, int* __restrict__ gate,
+                             tssvd_info* info) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int i = tid; i < k * k; i += 256) {
+    const int r = i / k, c = i - r * k;
+    const double d = G[i] - (r == c ? 1.0 : 0.0);
+    s = fma(d, d, s);
+  }
+  red[tid] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double o = sqrt(red[0]);
+    *ortho_out = o;
+    const int g = (mode == TSSVD_ORTHO_TWICE) || !(o <= tol);
+    *gate = g;
+    if (info) {
+      info->ortho = o;
+      info->reorth = g;
+    }
+  }
+}
+
+// T = R diag(S) (n x n), for the second orthonormalization of U = Q2 R2.
+__global__ void k_scale_cols(const double* __restrict__ R, const double* __restrict__ S, int n,
+                             double* __restrict__ T, const int* __restrict__ gate) {
+  if (*gate == 0) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n * n) T[i] = R[i] * S[i % n];
+}
+
+// C = A B for small n x n row-major matrices (one thread per output, fixed k order).
+__global__ void k_small_gemm(const double* __restrict__ A, const double* __restrict__ B, int n,
+                             double* __restrict__ C, const int* __restrict__ gate) {
+  if (*gate == 0) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * n) return;
+  const int r = i / n, c = i - r * n;
+  double s = 0.0;
+  for (int t = 0; t < n; ++t) s = fma(A[r * n + t], B[t * n + c], s);
+  C[i] = s;
+}
+
+struct TssvdWs {
+  TsqrPlan p;
+  double *Ut, *S, *Vt, *T, *P2, *S2, *W2, *V2, *G, *part, *ortho;
+  int* gate;
+  size_t bytes;
+};
+
+TssvdWs tssvd_layout(int64_t m, int n, void* work) {
+  TssvdWs w;
+  Carver c(work);
+  w.p = tsqr_plan(m, n);
+  tsqr_carve(w.p, c);
+  const size_t nn = (size_t)n * n;
+  w.Ut = c.take<double>(nn);
+  w.S = c.take<double>(n);
+  w.Vt = c.take<double>(nn);
+  w.T = c.take<double>(nn);
+  w.P2 = c.take<double>(nn);
+  w.S2 = c.take<double>(n);
+  w.W2 = c.take<double>(nn);
+  w.V2 = c.take<double>(nn);
+  w.G = c.take<double>(nn);
+  w.part = c.take<double>(atq_partials(m, n, n));
+  w.ortho = c.take<double>(1);
+  w.gate = c.take<int>(4);
+  w.bytes = c.off + 256;
+  return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tssvd_default_opts(tssvd_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->prec = TSSVD_PREC_FP64;
+  o->ortho = TSSVD_ORTHO_AUTO;
+  o->working_precision = 0.0;
+  o->reorth_tol = 1e-13;
+  o->max_jacobi_sweeps = 30;
+  o->seed = 0x9E3779B97F4A7C15ull;
+}
+
+const char* tssvd_status_string(int status) {
+  switch (status) {
+    case TSSVD_OK: return "ok";
+    case TSSVD_E_INVALID_ARG: return "invalid argument";
+    case TSSVD_E_WORKSPACE: return "workspace missing or too small";
+    case TSSVD_E_HIP: return "HIP launch failure";
+    case TSSVD_E_UNSUPPORTED: return "unsupported size or option";
+    default: return "unknown status";
+  }
+}
+
+int tssvd_version(void) { return VERSION; }
+
+// ---------------------------------------------------------------- tsqr
+int tsqr_workspace_bytes(int64_t m, int64_t n, int32_t a_dtype, size_t* bytes) {
+  if (!bytes || bad_dtype(a_dtype) || n < 1 || m < n) return TSSVD_E_INVALID_ARG;
+  if (n > TSSVD_TSQR_N_MAX) return TSSVD_E_UNSUPPORTED;
+  TsqrPlan p = tsqr_plan(m, (int)n);
+  Carver c(nullptr);
+  tsqr_carve(p, c);
+  c.take<double>((size_t)n * n);
+  *bytes = c.off + 256;
+  return TSSVD_OK;
+}
+
+int tsqr(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double* Q,
+         int64_t ldq, double* R, int64_t ldr, void* work, size_t work_bytes, void* stream) {
+  if (!A || !R || bad_dtype(a_dtype) || n < 1 || m < n || lda < n || ldr < n ||
+      (Q && ldq < n))
+    return TSSVD_E_INVALID_ARG;
+  if (n > TSSVD_TSQR_N_MAX) return TSSVD_E_UNSUPPORTED;
+  size_t need = 0;
+  tsqr_workspace_bytes(m, n, a_dtype, &need);
+  if (!work || work_bytes < need) return TSSVD_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  TsqrPlan p = tsqr_plan(m, (int)n);
+  Carver c(work);
+  tsqr_carve(p, c);
+  double* I = c.take<double>((size_t)n * n);
+  TRY(tsqr_factor(p, A, a_dtype, lda, s));
+  TRY(copy_matrix(tsqr_root(p), n, (int)n, n, R, ldr, s));
+  if (Q) {
+    TRY(fill_identity(I, (int)n, (int)n, s));
+    TRY(tsqr_apply(p, I, (int)n, Q, ldq, s));
+  }
+  return TSSVD_OK;
+}
+
+// ---------------------------------------------------------------- tssvd
+int tssvd_workspace_bytes(int64_t m, int64_t n, int32_t a_dtype, const tssvd_opts* opts,
+                          size_t* bytes) {
+  if (!bytes || bad_dtype(a_dtype) || n < 1 || m < n) return TSSVD_E_INVALID_ARG;
+  if (n > TSSVD_N_MAX) return TSSVD_E_UNSUPPORTED;
+  (void)opts;
+  *bytes = tssvd_layout(m, (int)n, nullptr).bytes;
+  return TSSVD_OK;
+}
+
+int tssvd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double* U,
+          int64_t ldu, double* S, double* V, int64_t ldv, tssvd_info* info, void* work,
+          size_t work_bytes, const tssvd_opts* opts, void* stream) {
+  if (!A || !U || !S || !V || bad_dtype(a_dtype) || n < 1 || m < n || lda < n || ldu < n ||
+      ldv < n)
+    return TSSVD_E_INVALID_ARG;
+  const tssvd_opts o = resolve(opts);
+  if (check_opts(o) != TSSVD_OK) return TSSVD_E_INVALID_ARG;
+  if (n > TSSVD_N_MAX) return TSSVD_E_UNSUPPORTED;
+  const int ni = (int)n;
+  TssvdWs w = tssvd_layout(m, ni, work);
+  if (!work || work_bytes < w.bytes) return TSSVD_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+
+  TRY(info_init(info, s));
+  // Algorithm 1: TSQR A = Q R; SVD R = U~ S V~^T (discard rule inside); U = Q U~.
+  TRY(tsqr_factor(w.p, A, a_dtype, lda, s, true));
+  TRY(jacobi_svd(tsqr_root(w.p), ni, ni, 0, o.working_precision, o.max_jacobi_sweeps, 1, w.Ut,
+                 w.S, w.Vt, info, s));
+  TRY(tsqr_apply(w.p, w.Ut, ni, U, ldu, s, true));
+  TRY(copy_matrix(w.S, 1, ni, ni, S, ni, s));
+  TRY(copy_matrix(w.Vt, n, ni, n, V, ldv, s));
+  if (o.ortho == TSSVD_ORTHO_ONCE) return TSSVD_OK;
+
+  // Second orthonormalization (Algorithm 2), written for U = Q2 R2:
+  //   A = Q2 (R2 diag(S)) V^T,  SVD(R2 diag(S)) = P S' W^T,  U' = Q2 P, V' = V W.
+  // The discard rule of Algorithm 2 step 5 tests the diagonal of R2.  Gate: always for
+  // TWICE; for AUTO when ||U^T U - I||_F > reorth_tol.  The host cannot read the gate
+  // without a synchronization, so the pass is always enqueued and every kernel of it
+  // returns at once when the gate is 0.
+  TRY(gemm_atq_f64(U, TSSVD_F64, ldu, m, n, U, (int)ldu, ni, w.G, ni, w.part, s));
+  hipLaunchKernelGGL(k_ortho_gate, dim3(1), dim3(256), 0, s, w.G, ni, o.ortho, o.reorth_tol,
+                     w.ortho, w.gate, info);
+  TsqrPlan p2 = w.p;
+  p2.gate = w.gate;
+  TRY(tsqr_factor(p2, U, TSSVD_F64, ldu, s));
+  hipLaunchKernelGGL(k_scale_cols, dim3((ni * ni + 255) / 256), dim3(256), 0, s,
+                     tsqr_root(p2), w.S, ni, w.T, w.gate);
+  TRY(jacobi_svd(w.T, ni, ni, 0, o.working_precision, o.max_jacobi_sweeps, 0, w.P2, w.S2,
+                 w.W2, info, s, w.gate, tsqr_root(p2), ni));
+  hipLaunchKernelGGL(k_small_gemm, dim3((ni * ni + 255) / 256), dim3(256), 0, s, w.Vt, w.W2,
+                     ni, w.V2, w.gate);
+  TRY(sign_fix_cols(w.V2, n, ni, ni, w.P2, ni, ni, s, w.gate));
+  TRY(tsqr_apply(p2, w.P2, ni, U, ldu, s));
+  TRY(copy_matrix(w.S2, 1, ni, ni, S, ni, s, w.gate));
+  TRY(copy_matrix(w.V2, n, ni, n, V, ldv, s, w.gate));
+  return hip_status(hipGetLastError());
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- lowrank_svd
+namespace {
+
+struct LowrankWs {
+  TsqrPlan pY, pZ;
+  double *X, *Y, *Z, *part, *I, *P, *sig, *W, *Wk, *G, *ortho, *Tq;
+  int* gate;
+  size_t bytes;
+};
+
+LowrankWs lowrank_layout(int64_t m, int64_t n, int k, int l, void* work) {
+  LowrankWs w;
+  Carver c(work);
+  w.pY = tsqr_plan(m, l);
+  tsqr_carve(w.pY, c);
+  w.pZ = tsqr_plan(n, l);
+  tsqr_carve(w.pZ, c);
+  w.X = c.take<double>((size_t)n * l);
+  w.Y = c.take<double>((size_t)m * l);
+  w.Z = c.take<double>((size_t)n * l);
+  size_t np = atq_partials(m, n, l);
+  const size_t np2 = atq_partials(m, l, l);
+  if (np2 > np) np = np2;
+  w.part = c.take<double>(np);
+  const size_t ll = (size_t)l * l;
+  w.I = c.take<double>(ll);
+  w.P = c.take<double>(ll);
+  w.sig = c.take<double>(l);
+  w.W = c.take<double>(ll);
+  w.Wk = c.take<double>((size_t)l * k);
+  w.G = c.take<double>(ll);
+  w.Tq = c.take<double>(ll);
+  w.ortho = c.take<double>(1);
+  w.gate = c.take<int>(4);
+  w.bytes = c.off + 256;
+  return w;
+}
+
+int lowrank_check(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, int64_t k,
+                  int64_t l, int64_t q) {
+  if (!A || bad_dtype(a_dtype) || m < 1 || n < 1 || lda < n) return TSSVD_E_INVALID_ARG;
+  if (!(0 < k && k <= l && l < m && l < n) || q < 0) return TSSVD_E_INVALID_ARG;
+  if (l > TSSVD_N_MAX) return TSSVD_E_UNSUPPORTED;
+  return TSSVD_OK;
+}
+
+// Orthonormal basis of span(Y) by TSQR, written over Y (m x l).
+hipError_t orth_inplace(const TsqrPlan& p, double* Y, int l, const double* I, hipStream_t s) {
+  hipError_t e = tsqr_factor(p, Y, TSSVD_F64, l, s);
+  if (e != hipSuccess) return e;
+  return tsqr_apply(p, I, l, Y, l, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lowrank_svd_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t l, int64_t q,
+                                int32_t a_dtype, const tssvd_opts* opts, size_t* bytes) {
+  if (!bytes) return TSSVD_E_INVALID_ARG;
+  int st = lowrank_check((const void*)1, a_dtype, m, n, n, k, l, q);
+  if (st != TSSVD_OK) return st;
+  (void)opts;
+  *bytes = lowrank_layout(m, n, (int)k, (int)l, nullptr).bytes;
+  return TSSVD_OK;
+}
+
+int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, int64_t k,
+                int64_t l, int64_t q, const double* Omega, double* U, int64_t ldu, double* S,
+                double* V, int64_t ldv, tssvd_info* info, void* work, size_t work_bytes,
+                const tssvd_opts* opts, void* stream) {
+  int st = lowrank_check(A, a_dtype, m, n, lda, k, l, q);
+  if (st != TSSVD_OK) return st;
+  if (!U || !S || !V || ldu < k || ldv < k) return TSSVD_E_INVALID_ARG;
+  const tssvd_opts o = resolve(opts);
+  if (check_opts(o) != TSSVD_OK) return TSSVD_E_INVALID_ARG;
+  if (o.prec != TSSVD_PREC_FP64) return TSSVD_E_UNSUPPORTED;
+  if (o.working_precision > 0.0) return TSSVD_E_UNSUPPORTED;
+  const int ki = (int)k, li = (int)l;
+  LowrankWs w = lowrank_layout(m, n, ki, li, work);
+  if (!work || work_bytes < w.bytes) return TSSVD_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+
+  TRY(info_init(info, s));
+  TRY(fill_identity(w.I, li, li, s));
+  if (Omega)
+    TRY(copy_matrix(Omega, n, li, l, w.X, l, s));
+  else
+    TRY(philox_sketch(w.X, n, li, o.seed, s));
+  // Algorithm 5: subspace iteration
+  TRY(gemm_ax_f64(A, a_dtype, lda, m, n, w.X, li, li, w.Y, li, s, TSSVD_PROF_AX));  // A Q~_0
+  for (int64_t j = 0; j < q; ++j) {
+    TRY(orth_inplace(w.pY, w.Y, li, w.I, s));                                  // Q_j
+    TRY(gemm_atq_f64(A, a_dtype, lda, m, n, w.Y, li, li, w.Z, li, w.part, s,
+                     TSSVD_PROF_ATQ));                                         // A^* Q_j
+    TRY(orth_inplace(w.pZ, w.Z, li, w.I, s));                                  // Q~_j
+    TRY(gemm_ax_f64(A, a_dtype, lda, m, n, w.Z, li, li, w.Y, li, s, TSSVD_PROF_AX));  // A Q~_j
+  }
+  TRY(orth_inplace(w.pY, w.Y, li, w.I, s));                                    // Q
+  if (o.ortho != TSSVD_ORTHO_ONCE) {
+    // last step orthonormalized twice (Algorithm 2 form), gated like tssvd
+    TRY(gemm_atq_f64(w.Y, TSSVD_F64, l, m, l, w.Y, li, li, w.G, li, w.part, s));
+    hipLaunchKernelGGL(k_ortho_gate, dim3(1), dim3(256), 0, s, w.G, li, o.ortho, o.reorth_tol,
+                       w.ortho, w.gate, info);
+    TsqrPlan p2 = w.pY;
+    p2.gate = w.gate;
+    TRY(tsqr_factor(p2, w.Y, TSSVD_F64, l, s));
+    TRY(tsqr_apply(p2, w.I, li, w.Y, l, s));
+  }
+  // Algorithm 6: B = Q^* A via B^* = A^* Q = Q_B R_B;  R_B^T = P S W^T  =>
+  //   B = P S (Q_B W)^T,  U = Q P_k,  V = Q_B W_k.
+  TRY(gemm_atq_f64(A, a_dtype, lda, m, n, w.Y, li, li, w.Z, li, w.part, s, TSSVD_PROF_ATQ));
+  TRY(tsqr_factor(w.pZ, w.Z, TSSVD_F64, l, s));
+  TRY(jacobi_svd(tsqr_root(w.pZ), li, li, 1, 0.0, o.max_jacobi_sweeps, 0, w.P, w.sig, w.W,
+                 info, s));
+  TRY(copy_matrix(w.W, l, ki, l, w.Wk, k, s));
+  TRY(tsqr_apply(w.pZ, w.Wk, ki, V, ldv, s));
+  TRY(sign_fix_cols(V, n, (int)ldv, ki, w.P, li, li, s));
+  TRY(gemm_ax_f64(w.Y, TSSVD_F64, l, m, l, w.P, li, ki, U, (int)ldu, s));
+  TRY(copy_matrix(w.sig, 1, ki, k, S, k, s));
+  return hip_status(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- lowrank_svd_backward
+int lowrank_svd_backward_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t l, int64_t q,
+                                         int32_t a_dtype, const tssvd_opts* opts,
+                                         size_t* bytes) {
+  if (!bytes) return TSSVD_E_INVALID_ARG;
+  int st = lowrank_check((const void*)1, a_dtype, m, n, n, k, l, q);
+  if (st != TSSVD_OK) return st;
+  (void)opts;
+  return TSSVD_E_UNSUPPORTED;
+}
+
+int lowrank_svd_backward(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
+                         int64_t k, int64_t l, int64_t q, const double* Omega, const double* U,
+                         int64_t ldu, const double* S, const double* V, int64_t ldv,
+                         const double* gU, const double* gS, const double* gV, void* gA,
+                         int64_t ldga, tssvd_info* info, void* work, size_t work_bytes,
+                         const tssvd_opts* opts, void* stream) {
+  int st = lowrank_check(A, a_dtype, m, n, lda, k, l, q);
+  if (st != TSSVD_OK) return st;
+  (void)Omega; (void)U; (void)ldu; (void)S; (void)V; (void)ldv; (void)gU; (void)gS; (void)gV;
+  (void)gA; (void)ldga; (void)info; (void)work; (void)work_bytes; (void)opts; (void)stream;
+  return TSSVD_E_UNSUPPORTED;
+}
+
+// ---------------------------------------------------------------- measurement support
+int tssvd_profile_enable(int on) {
+  prof_enable(on != 0);
+  return TSSVD_OK;
+}
+
+int tssvd_profile_read(int kind, double* total_ms, int64_t* launches) {
+  if (kind < 0 || kind >= TSSVD_PROF_KINDS || !total_ms || !launches) return TSSVD_E_INVALID_ARG;
+  return prof_read(kind, total_ms, launches) == hipSuccess ? TSSVD_OK : TSSVD_E_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,265 @@
+// Products with the large matrix A on gfx950 matrix cores (float64 path).
+//
+//   Y = A X   (m x n times n x l)   Algorithm 5 steps 2 and 9 (sketch and power steps)
+//   Z = A^T Q (n x m times m x l)   Algorithm 5 step 5 and Algorithm 6 step 1 (B^* = A^* Q)
+//
+// Both stream A once.  They use v_mfma_f64_16x16x4_f64 (D += A(16x4) B(4x16)); per lane:
+// A operand a[i = lane%16][k = lane/16], B operand b[k = lane/16][j = lane%16], result
+// register r holds D[4*r + lane/16][lane%16] (measured on gfx950; the float32 16x16x4
+// form instead holds D[4*(lane/16) + r][lane%16]).  The contraction index k may be mapped
+// to any four values as long as A and B operands use the same map; both kernels use that
+// freedom to give each lane contiguous runs of A.
+//
+// Z = A^T Q is split over row chunks of A ("split-K"); every (chunk, column tile) writes
+// its partial n_tile x l block and a second kernel adds the chunks in chunk order, so
+// the result is bitwise reproducible.  Workgroups sharing a row chunk are placed on the
+// same XCD (workgroup IDs are dealt to the 8 XCDs round-robin) so the chunk of Q they
+// all read stays in that XCD's L2.
+#include "common.h"
+#include "internal.h"
+
+namespace tsv {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- Y = A X
+// 256 threads; wave w owns rows base + 16*(RT*w + rt) + (0..15); all NT column tiles.
+// Per step of 16 along k, lane (i = lane%16, g = lane/16) loads A[row][k0+4g .. k0+4g+3]
+// and uses element s in the s-th MFMA: k-slot g of MFMA s is column k0 + 4g + s.
+template <int RT, int NT, typename TA>
+__global__ __launch_bounds__(256) void k_gemm_ax_f64(const TA* __restrict__ A, int64_t lda,
+                                                     int64_t m, int n,
+                                                     const double* __restrict__ X, int ldx,
+                                                     int l, double* __restrict__ Y, int ldy) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t rbase = (int64_t)blockIdx.x * (64 * RT) + (int64_t)wave * (16 * RT);
+  f64x4 acc[RT][NT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const TA* arow[RT];
+  bool rok[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int64_t row = rbase + 16 * rt + li;
+    rok[rt] = row < m;
+    arow[rt] = A + (rok[rt] ? row : 0) * lda;
+  }
+  for (int k0 = 0; k0 < n; k0 += 16) {
+    double a[RT][4], x[NT][4];
+    const int kb = k0 + 4 * g;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int kk = kb + s;
+      const bool kok = kk < n;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) a[rt][s] = (kok && rok[rt]) ? ld_elem(arow[rt] + kk) : 0.0;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int col = 16 * nt + li;
+        x[nt][s] = (kok && col < l) ? X[(int64_t)kk * ldx + col] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mfma_f64(a[rt][s], x[nt][s], acc[rt][nt]);
+  }
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int col = 16 * nt + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = rbase + 16 * rt + 4 * r + g;
+        if (row < m && col < l) Y[row * ldy + col] = acc[rt][nt][r];
+      }
+    }
+}
+
+template <int NT, typename TA>
+static void launch_ax(const TA* A, int64_t lda, int64_t m, int64_t n, const double* X,
+                      int ldx, int l, double* Y, int ldy, hipStream_t s) {
+  constexpr int RT = 2;
+  const int64_t grid = (m + 64 * RT - 1) / (64 * RT);
+  hipLaunchKernelGGL((k_gemm_ax_f64<RT, NT, TA>), dim3((unsigned)grid), dim3(256), 0, s, A,
+                     lda, m, (int)n, X, ldx, l, Y, ldy);
+}
+
+template <typename TA>
+static hipError_t ax_dispatch(const TA* A, int64_t lda, int64_t m, int64_t n, const double* X,
+                              int ldx, int l, double* Y, int ldy, hipStream_t s) {
+  const int nt = (l + 15) / 16;
+  switch (nt) {
+    case 1: launch_ax<1>(A, lda, m, n, X, ldx, l, Y, ldy, s); break;
+    case 2: launch_ax<2>(A, lda, m, n, X, ldx, l, Y, ldy, s); break;
+    case 3: launch_ax<3>(A, lda, m, n, X, ldx, l, Y, ldy, s); break;
+    case 4: launch_ax<4>(A, lda, m, n, X, ldx, l, Y, ldy, s); break;
+    case 5: launch_ax<5>(A, lda, m, n, X, ldx, l, Y, ldy, s); break;
+    case 6: launch_ax<6>(A, lda, m, n, X, ldx, l, Y, ldy, s); break;
+    case 7: launch_ax<7>(A, lda, m, n, X, ldx, l, Y, ldy, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t gemm_ax_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int64_t n,
+                       const double* X, int ldx, int l, double* Y, int ldy, hipStream_t s,
+                       int prof) {
+  prof_begin(prof, s);
+  hipError_t e = (a_dtype == TSSVD_F64)
+                     ? ax_dispatch((const double*)A, lda, m, n, X, ldx, l, Y, ldy, s)
+                     : ax_dispatch((const float*)A, lda, m, n, X, ldx, l, Y, ldy, s);
+  prof_end(prof, s);
+  return e;
+}
+
+// ---------------------------------------------------------------- Z = A^T Q
+// Workgroup = (row chunk, 256-column tile); wave w owns columns c0 + 64w .. c0 + 64w + 63.
+// Output rows of the MFMA are columns of A: tile mt (0..3) covers columns cw + 4*i + mt
+// (i = 0..15), so lane (i, g) reads the four contiguous values A[row][cw+4i .. cw+4i+3].
+// The contraction runs over rows: in one MFMA, k-slot g is row r + g.
+constexpr int ATQ_COLS = 256;
+
+template <int NT, typename TA>
+__global__ __launch_bounds__(256) void k_gemm_atq_f64(const TA* __restrict__ A, int64_t lda,
+                                                      int64_t m, int n,
+                                                      const double* __restrict__ Q, int ldq,
+                                                      int l, int ncol, int nchunk,
+                                                      int64_t chunk_rows,
+                                                      double* __restrict__ part) {
+  const int total = ncol * nchunk;
+  const int per = (total + 7) / 8;
+  const int L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (L >= total) return;
+  const int chunk = L / ncol, ct = L - chunk * ncol;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int cw = ct * ATQ_COLS + 64 * wave;
+  if (cw >= n) return;
+  const int64_t r0 = (int64_t)chunk * chunk_rows;
+  const int64_t r1 = (r0 + chunk_rows < m) ? r0 + chunk_rows : m;
+  f64x4 acc[4][NT];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int cb = cw + 4 * li;
+  for (int64_t rq = r0; rq < r1; rq += 4) {
+    const int64_t row = rq + g;
+    const bool rok = row < r1;
+    const int64_t rr = rok ? row : r0;
+    double a[4], q[NT];
+    const TA* ap = A + rr * lda + cb;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) a[mt] = (rok && cb + mt < n) ? ld_elem(ap + mt) : 0.0;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int col = 16 * nt + li;
+      q[nt] = (rok && col < l) ? Q[rr * ldq + col] : 0.0;
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_f64(a[mt], q[nt], acc[mt][nt]);
+  }
+  double* P = part + (int64_t)chunk * n * l;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int col = 16 * nt + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * r + g;          // MFMA output row
+        const int c = cw + 4 * i + mt;    // column of A
+        if (c < n && col < l) P[(int64_t)c * l + col] = acc[mt][nt][r];
+      }
+    }
+}
+
+__global__ void k_reduce_chunks(const double* __restrict__ part, int nchunk, int64_t count,
+                                double* __restrict__ Z, int l, int ldz) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * count + idx];
+  const int64_t row = idx / l;
+  const int col = (int)(idx - row * l);
+  Z[row * ldz + col] = s;
+}
+
+static void atq_grid(int64_t m, int64_t n, int& ncol, int& nchunk, int64_t& chunk_rows) {
+  ncol = (int)((n + ATQ_COLS - 1) / ATQ_COLS);
+  int64_t want = (1024 + ncol - 1) / ncol;
+  const int64_t maxc = (m + 255) / 256;
+  if (want > maxc) want = maxc;
+  if (want < 1) want = 1;
+  chunk_rows = (m + want - 1) / want;
+  chunk_rows = (chunk_rows + 15) / 16 * 16;
+  nchunk = (int)((m + chunk_rows - 1) / chunk_rows);
+}
+
+size_t atq_partials(int64_t m, int64_t n, int l) {
+  int ncol, nchunk;
+  int64_t cr;
+  atq_grid(m, n, ncol, nchunk, cr);
+  return (size_t)nchunk * n * l;
+}
+
+template <int NT, typename TA>
+static void launch_atq(const TA* A, int64_t lda, int64_t m, int64_t n, const double* Q, int ldq,
+                       int l, double* part, hipStream_t s) {
+  int ncol, nchunk;
+  int64_t cr;
+  atq_grid(m, n, ncol, nchunk, cr);
+  const int total = ncol * nchunk;
+  const int grid = ((total + 7) / 8) * 8;
+  hipLaunchKernelGGL((k_gemm_atq_f64<NT, TA>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
+                     Q, ldq, l, ncol, nchunk, cr, part);
+}
+
+template <typename TA>
+static hipError_t atq_dispatch(const TA* A, int64_t lda, int64_t m, int64_t n, const double* Q,
+                               int ldq, int l, double* part, hipStream_t s) {
+  switch ((l + 15) / 16) {
+    case 1: launch_atq<1>(A, lda, m, n, Q, ldq, l, part, s); break;
+    case 2: launch_atq<2>(A, lda, m, n, Q, ldq, l, part, s); break;
+    case 3: launch_atq<3>(A, lda, m, n, Q, ldq, l, part, s); break;
+    case 4: launch_atq<4>(A, lda, m, n, Q, ldq, l, part, s); break;
+    case 5: launch_atq<5>(A, lda, m, n, Q, ldq, l, part, s); break;
+    case 6: launch_atq<6>(A, lda, m, n, Q, ldq, l, part, s); break;
+    case 7: launch_atq<7>(A, lda, m, n, Q, ldq, l, part, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t gemm_atq_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int64_t n,
+                        const double* Q, int ldq, int l, double* Z, int ldz, double* part,
+                        hipStream_t s, int prof) {
+  prof_begin(prof, s);
+  hipError_t e = (a_dtype == TSSVD_F64)
+                     ? atq_dispatch((const double*)A, lda, m, n, Q, ldq, l, part, s)
+                     : atq_dispatch((const float*)A, lda, m, n, Q, ldq, l, part, s);
+  prof_end(prof, s);
+  if (e != hipSuccess) return e;
+  int ncol, nchunk;
+  int64_t cr;
+  atq_grid(m, n, ncol, nchunk, cr);
+  const int64_t count = n * (int64_t)l;
+  hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                     part, nchunk, count, Z, l, ldz);
+  return hipGetLastError();
+}
+
+}  // namespace tsv

@@ -1,0 +1,99 @@
+// Host-side launchers shared between the kernel translation units and the C ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/tssvd.h"
+
+namespace tsv {
+
+// ------------------------------------------------------------------ workspace carving
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// ------------------------------------------------------------------ TSQR
+// Row blocks of B = 16*NR rows; each leaf workgroup reduces `bpw` consecutive blocks.
+struct TsqrPlan {
+  int64_t m = 0;
+  int n = 0;
+  int nc = 0, nr = 0, B = 0;
+  int64_t nblocks = 0;
+  int W = 0;             // leaf workgroups
+  int bpw = 0;           // blocks per leaf workgroup
+  std::vector<int> cnt;  // cnt[0] = W, cnt[L+1] = ceil(cnt[L]/2), last = 1
+  // workspace regions (filled by carve)
+  double* Vleaf = nullptr;  // nblocks * n * B   reflector tails, column-major per block
+  double* tauleaf = nullptr;  // nblocks * n
+  std::vector<double*> Rlev;  // per level: cnt[L] * n * n
+  std::vector<double*> Vtree; // per level L (merges producing level L+1): cnt[L+1] * n * B
+  std::vector<double*> tautree;
+  std::vector<double*> Slev;  // seeds per level: cnt[L] * n * n
+  // When non-NULL, every kernel of the plan returns at once if *gate == 0 (device flag).
+  const int* gate = nullptr;
+};
+
+TsqrPlan tsqr_plan(int64_t m, int n);
+void tsqr_carve(TsqrPlan& p, Carver& c);
+// Factor: leaf blocks + tree.  After it, root R (n x n, upper, row-major) is tsqr_root(p).
+hipError_t tsqr_factor(const TsqrPlan& p, const void* A, int a_dtype, int64_t lda,
+                       hipStream_t s, bool prof = false);
+double* tsqr_root(const TsqrPlan& p);
+// Apply: Q [S; 0] for a root seed S (n x k, row-major, stride k, device), written to
+// out (m x k, stride ldo).  S is copied first, so it may live anywhere.
+hipError_t tsqr_apply(const TsqrPlan& p, const double* S, int k, double* out, int64_t ldo,
+                      hipStream_t s, bool prof = false);
+
+// ------------------------------------------------------------------ small SVD (Jacobi)
+// SVD of M (n x n row-major, stride ldm; its transpose when transpose != 0):
+//   M = Uo diag(So) Vo^T, columns sorted by descending singular value.
+// wp > 0 zeroes the rows j with |M_jj| < wp |M_00| first (discard rule) and zeroes the
+// triplets past the kept rank; the diagonal tested is that of dsrc (stride ldd) when
+// given, else M's.  sign_fix orients pairs so that w^T v_j >= 0.
+hipError_t jacobi_svd(const double* M, int ldm, int n, int transpose, double wp,
+                      int max_sweeps, int sign_fix, double* Uo, double* So, double* Vo,
+                      tssvd_info* info, hipStream_t s, const int* gate = nullptr,
+                      const double* dsrc = nullptr, int ldd = 0);
+
+// ------------------------------------------------------------------ products with A
+// Y (m x l, stride ldy) = A (m x n) X (n x l, stride ldx), float64 accumulation.
+hipError_t gemm_ax_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int64_t n,
+                       const double* X, int ldx, int l, double* Y, int ldy, hipStream_t s,
+                       int prof = -1);
+// Z (n x l, stride ldz) = A^T (n x m) Q (m x l, stride ldq).  Split over row chunks into
+// `part` (size atq_partials(m, n, l) doubles), reduced in a fixed order.
+size_t atq_partials(int64_t m, int64_t n, int l);
+hipError_t gemm_atq_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int64_t n,
+                        const double* Q, int ldq, int l, double* Z, int ldz, double* part,
+                        hipStream_t s, int prof = -1);
+
+// ------------------------------------------------------------------ misc
+hipError_t fill_identity(double* S, int n, int k, hipStream_t s);
+hipError_t philox_sketch(double* X, int64_t n, int l, uint64_t seed, hipStream_t s);
+// Orient columns of V (n x k) so that w^T v_j >= 0; flip the same columns of P (rows x k,
+// stride ldp) and of V.
+hipError_t sign_fix_cols(double* V, int64_t n, int ldv, int k, double* P, int prow, int ldp,
+                         hipStream_t s, const int* gate = nullptr);
+hipError_t copy_matrix(const double* src, int64_t rows, int cols, int64_t lds, double* dst,
+                       int64_t ldd, hipStream_t s, const int* gate = nullptr);
+hipError_t info_init(tssvd_info* info, hipStream_t s);
+
+// measurement markers (no-ops unless tssvd_profile_enable(1) was called); kind < 0 = none
+void prof_begin(int kind, hipStream_t s);
+void prof_end(int kind, hipStream_t s);
+void prof_enable(bool on);
+hipError_t prof_read(int kind, double* total_ms, int64_t* launches);
+
+}  // namespace tsv

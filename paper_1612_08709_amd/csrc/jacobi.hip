@@ -1,0 +1,187 @@
+// Small dense SVD on one workgroup (gfx950): one-sided Jacobi (Hestenes) in float64.
+//
+// Algorithm 1 step 4 / Algorithm 2 step 7 / Algorithm 6 step 2 need the SVD of a small
+// n x n factor (n <= 100).  One-sided Jacobi orthogonalizes the columns of M by plane
+// rotations applied on the right, accumulating them in V:  M J1 J2 ... = U Sigma,
+// V = J1 J2 ...; at convergence sigma_j = ||M e_j||, u_j = M e_j / sigma_j.  It attains
+// the accuracy of a backward-stable SVD and needs only column dot products, which map
+// onto 16-lane DPP reductions.
+//
+// Layout: M and V column-major in the 160 KB local data share (n*n doubles each).
+// 1024 threads = 64 groups of 16 lanes; per round of the round-robin ("circle") ordering
+// the <= 50 disjoint column pairs go to distinct groups, and a barrier separates rounds.
+// A sweep is the n'-1 rounds (n' = n rounded up to even) that visit every pair once.
+// A pair is rotated when |m_p^T m_q| > tol sqrt(|m_p|^2 |m_q|^2), tol = sqrt(n) * eps;
+// iteration stops after the first sweep without rotations or at max_sweeps.
+#include <float.h>
+
+#include "common.h"
+#include "internal.h"
+
+namespace tsv {
+
+constexpr int JAC_THREADS = 1024;
+
+__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(
+    const double* __restrict__ M0, int ldm, int n, int transpose, double wp, int max_sweeps,
+    int sign_fix, double* __restrict__ Uo, double* __restrict__ So, double* __restrict__ Vo,
+    tssvd_info* __restrict__ info, const int* __restrict__ gate,
+    const double* __restrict__ dsrc, int ldd) {
+  if (gate && *gate == 0) return;
+  extern __shared__ double smem[];
+  double* M = smem;          // column c at M + c*n
+  double* V = smem + n * n;  // column c at V + c*n
+  __shared__ int s_rot;
+  __shared__ int s_rank;
+  __shared__ double s_sig[TSSVD_N_MAX];
+  __shared__ int s_pos[TSSVD_N_MAX];
+  __shared__ double s_sgn[TSSVD_N_MAX];
+  const int tid = threadIdx.x;
+  const int lane16 = tid & 15, grp = tid >> 4;
+
+  // load (M column c, row i) = M0[i][c], or M0[c][i] for the transposed input
+  for (int idx = tid; idx < n * n; idx += JAC_THREADS) {
+    const int c = idx / n, i = idx - c * n;
+    M[idx] = transpose ? M0[c * ldm + i] : M0[i * ldm + c];
+    V[idx] = (c == i) ? 1.0 : 0.0;
+  }
+  if (tid == 0) s_rank = n;
+  __syncthreads();
+  // discard rule: drop row j when |D_jj| < wp |D_00|, D = dsrc (the triangular factor
+  // whose diagonal decides) or M itself
+  if (wp > 0.0) {
+    const double thr = wp * fabs(dsrc ? dsrc[0] : M[0]);
+    if (tid < n) {
+      const int j = tid;
+      const double djj = dsrc ? dsrc[j * ldd + j] : M[j * n + j];
+      if (fabs(djj) < thr) {
+        for (int c = 0; c < n; ++c) M[c * n + j] = 0.0;
+        atomicSub(&s_rank, 1);
+      }
+    }
+    __syncthreads();
+  }
+
+  const double tol = sqrt((double)n) * DBL_EPSILON;
+  const int np = (n + 1) & ~1;  // players in the circle method
+  int sweep = 0;
+  bool converged = (n < 2);
+  while (!converged && sweep < max_sweeps) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int t = 0; t < np - 1; ++t) {
+      if (grp < np / 2) {
+        int p, q;
+        if (grp == 0) {
+          p = t;
+          q = np - 1;
+        } else {
+          p = (t + grp) % (np - 1);
+          q = (t - grp + (np - 1)) % (np - 1);
+        }
+        if (p > q) { const int tmp = p; p = q; q = tmp; }
+        if (q < n) {
+          double* mp = M + p * n;
+          double* mq = M + q * n;
+          double al = 0.0, be = 0.0, ga = 0.0;
+          for (int i = lane16; i < n; i += 16) {
+            const double x = mp[i], y = mq[i];
+            al = fma(x, x, al);
+            be = fma(y, y, be);
+            ga = fma(x, y, ga);
+          }
+          al = sum16(al);
+          be = sum16(be);
+          ga = sum16(ga);
+          if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+            const double c = 1.0 / sqrt(fma(tt, tt, 1.0));
+            const double s = c * tt;
+            for (int i = lane16; i < n; i += 16) {
+              const double x = mp[i], y = mq[i];
+              mp[i] = fma(c, x, -s * y);
+              mq[i] = fma(s, x, c * y);
+            }
+            double* vp = V + p * n;
+            double* vq = V + q * n;
+            for (int i = lane16; i < n; i += 16) {
+              const double x = vp[i], y = vq[i];
+              vp[i] = fma(c, x, -s * y);
+              vq[i] = fma(s, x, c * y);
+            }
+            if (lane16 == 0) s_rot = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    ++sweep;
+    converged = (s_rot == 0);
+    __syncthreads();
+  }
+
+  // singular values = column norms; sign of each pair from w^T v_j
+  for (int c = grp; c < n; c += JAC_THREADS / 16) {
+    double s2 = 0.0, sw = 0.0;
+    for (int i = lane16; i < n; i += 16) {
+      s2 = fma(M[c * n + i], M[c * n + i], s2);
+      sw = fma(sign_ref(i), V[c * n + i], sw);
+    }
+    s2 = sum16(s2);
+    sw = sum16(sw);
+    if (lane16 == 0) {
+      s_sig[c] = sqrt(s2);
+      s_sgn[c] = (sign_fix && sw < 0.0) ? -1.0 : 1.0;
+    }
+  }
+  __syncthreads();
+  // descending order; ties keep the original column order
+  if (tid < n) {
+    const double sj = s_sig[tid];
+    int pos = 0;
+    for (int i = 0; i < n; ++i) {
+      const double si = s_sig[i];
+      pos += (si > sj) || (si == sj && i < tid);
+    }
+    s_pos[tid] = pos;
+  }
+  __syncthreads();
+  const int rank = s_rank;
+  for (int idx = tid; idx < n * n; idx += JAC_THREADS) {
+    const int c = idx / n, i = idx - c * n;
+    const int pos = s_pos[c];
+    const double sg = s_sig[c];
+    const bool keep = pos < rank && sg > 0.0;
+    const double f = s_sgn[c];
+    Uo[i * n + pos] = keep ? f * M[idx] / sg : 0.0;
+    Vo[i * n + pos] = (pos < rank) ? f * V[idx] : 0.0;
+  }
+  if (tid < n) So[s_pos[tid]] = (s_pos[tid] < rank) ? s_sig[tid] : 0.0;
+  if (tid == 0 && info) {
+    int st = converged ? 0 : NUM_NO_CONVERGENCE;
+    for (int i = 0; i < n; ++i)
+      if (!isfinite(s_sig[i])) st |= NUM_NONFINITE;
+    atomicOr(&info->numstat, st);
+    info->rank = rank;
+    info->sweeps = sweep;
+  }
+}
+
+hipError_t jacobi_svd(const double* M, int ldm, int n, int transpose, double wp,
+                      int max_sweeps, int sign_fix, double* Uo, double* So, double* Vo,
+                      tssvd_info* info, hipStream_t s, const int* gate,
+                      const double* dsrc, int ldd) {
+  const size_t lds = (size_t)2 * n * n * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)(2 * TSSVD_N_MAX * TSSVD_N_MAX * sizeof(double)));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(JAC_THREADS), lds, s, M, ldm, n, transpose, wp,
+                     max_sweeps, sign_fix, Uo, So, Vo, info, gate, dsrc, ldd);
+  return hipGetLastError();
+}
+
+}  // namespace tsv

@@ -1,0 +1,129 @@
+"""The C ABI library: builds, loads, exports every declared symbol, validates on the host.
+
+No compute call runs here (no GPU in this environment); every call below returns
+from host-side argument validation before anything is enqueued.
+"""
+import ctypes as C
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tssvd.h")
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_1612_08709_amd import _native as N
+    if not os.path.exists(N.LIB_PATH):
+        from paper_1612_08709_amd import build
+        build.build(verbose=False)
+    return N
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_abi():
+    names = _declared_functions()
+    for f in ("tsqr", "tssvd", "lowrank_svd", "lowrank_svd_backward", "tssvd_workspace_bytes"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(native):
+    lib = native.lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", native.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    for name in _declared_functions():
+        assert name in exported, name
+        assert hasattr(lib, name)
+    assert set(native.EXPORTS) == set(_declared_functions())
+
+
+def test_default_opts_and_strings(native):
+    o = native.default_opts()
+    assert o.prec == native.PREC_FP64 and o.ortho == native.ORTHO_AUTO
+    assert o.working_precision == 0.0 and o.reorth_tol == 1e-13 and o.max_jacobi_sweeps == 30
+    assert native.status_string(0) == "ok"
+    assert "workspace" in native.status_string(2)
+    assert native.lib().tssvd_version() >= 100
+
+
+def test_struct_layouts_match_header(native):
+    assert C.sizeof(native.Opts) == 40
+    assert C.sizeof(native.Info) == 24
+
+
+def test_workspace_queries_validate(native):
+    lib, N = native.lib(), native
+    nb = C.c_size_t()
+    o = N.default_opts()
+    assert lib.tssvd_workspace_bytes(1000, 20, N.F64, C.byref(o), C.byref(nb)) == N.OK
+    assert nb.value > 1000 * 20 * 8
+    assert lib.tssvd_workspace_bytes(10, 20, N.F64, C.byref(o), C.byref(nb)) == N.E_INVALID_ARG
+    assert lib.tssvd_workspace_bytes(1000, 0, N.F64, C.byref(o), C.byref(nb)) == N.E_INVALID_ARG
+    assert lib.tssvd_workspace_bytes(1000, 20, 7, C.byref(o), C.byref(nb)) == N.E_INVALID_ARG
+    assert lib.tssvd_workspace_bytes(10**6, 101, N.F64, C.byref(o), C.byref(nb)) == N.E_UNSUPPORTED
+    assert lib.tsqr_workspace_bytes(10**6, 128, N.F64, C.byref(nb)) == N.OK
+    assert lib.tsqr_workspace_bytes(10**6, 129, N.F64, C.byref(nb)) == N.E_UNSUPPORTED
+    # lowrank: 0 < k <= l < min(m, n), q >= 0
+    ok = lib.lowrank_svd_workspace_bytes(2000, 500, 10, 20, 2, N.F32, C.byref(o), C.byref(nb))
+    assert ok == N.OK and nb.value > 2000 * 20 * 8
+    for (m, n, k, l, q) in [(2000, 500, 21, 20, 2), (2000, 500, 0, 20, 2), (2000, 20, 5, 20, 2),
+                            (20, 500, 5, 20, 2), (2000, 500, 5, 20, -1)]:
+        assert lib.lowrank_svd_workspace_bytes(m, n, k, l, q, N.F64, C.byref(o),
+                                               C.byref(nb)) == N.E_INVALID_ARG
+
+
+def test_calls_reject_bad_arguments_before_any_work(native):
+    lib, N = native.lib(), native
+    o = N.default_opts()
+    null = C.c_void_p(0)
+    fake = C.c_void_p(256)  # never dereferenced: validation fails first
+    # null A
+    assert lib.tssvd(null, N.F64, 100, 10, 10, fake, 10, fake, fake, 10, null, fake, 1 << 30,
+                     C.byref(o), null) == N.E_INVALID_ARG
+    # lda < n
+    assert lib.tssvd(fake, N.F64, 100, 10, 9, fake, 10, fake, fake, 10, null, fake, 1 << 30,
+                     C.byref(o), null) == N.E_INVALID_ARG
+    # workspace too small
+    assert lib.tssvd(fake, N.F64, 100, 10, 10, fake, 10, fake, fake, 10, null, fake, 16,
+                     C.byref(o), null) == N.E_WORKSPACE
+    assert lib.tssvd(fake, N.F64, 100, 10, 10, fake, 10, fake, fake, 10, null, null, 1 << 30,
+                     C.byref(o), null) == N.E_WORKSPACE
+    # bad option values
+    bad = N.default_opts()
+    bad.ortho = 9
+    assert lib.tssvd(fake, N.F64, 100, 10, 10, fake, 10, fake, fake, 10, null, fake, 1 << 30,
+                     C.byref(bad), null) == N.E_INVALID_ARG
+    bad = N.default_opts()
+    bad.working_precision = float("nan")
+    assert lib.tssvd(fake, N.F64, 100, 10, 10, fake, 10, fake, fake, 10, null, fake, 1 << 30,
+                     C.byref(bad), null) == N.E_INVALID_ARG
+    assert lib.tsqr(fake, N.F64, 5, 10, 10, null, 10, fake, 10, fake, 1 << 30, null) == N.E_INVALID_ARG
+    assert lib.lowrank_svd(fake, N.F64, 100, 50, 50, 8, 4, 1, null, fake, 8, fake, fake, 8, null,
+                           fake, 1 << 30, C.byref(o), null) == N.E_INVALID_ARG
+    assert lib.lowrank_svd(fake, N.F64, 100, 50, 50, 4, 8, 1, null, fake, 4, fake, fake, 4, null,
+                           fake, 16, C.byref(o), null) == N.E_WORKSPACE
+
+
+def test_sign_reference_constant_is_the_golden_ratio_conjugate():
+    """The device source spells g = (sqrt(5)-1)/2 as a decimal literal; it must be that double."""
+    src = open(os.path.join(ROOT, "paper_1612_08709_amd", "csrc", "common.h")).read()
+    lit = float(re.search(r"const double g = ([0-9.]+);", src).group(1))
+    assert lit == (math.sqrt(5.0) - 1.0) / 2.0
+
+
+def test_python_layer_fails_loudly_without_gpu_tensors(native):
+    import torch
+    import paper_1612_08709_amd as T
+    with pytest.raises(ValueError):
+        T.tssvd(torch.zeros(10, 3, dtype=torch.float64))

@@ -1,0 +1,136 @@
+"""GPU parity: tsqr and tssvd (Algorithms 1-2) through the C ABI vs the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import checks
+from oracle.tssvd_ref import tssvd_ref
+from synth import matrices as sm
+
+from gpu_util import col_sin, dev, flush_print, host, sigma_rel
+
+pytestmark = pytest.mark.gpu
+
+T = pytest.importorskip("paper_1612_08709_amd")
+
+
+def _graded(m, n, seed, cond=1e4):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((m, n)) * np.logspace(0, -np.log10(cond), n)
+
+
+def _run(A64, dtype=torch.float64, **kw):
+    A = dev(A64, dtype)
+    U, S, V, info = T.tssvd(A, **kw)
+    torch.cuda.synchronize()
+    return host(U), host(S), host(V), info
+
+
+def test_workload1_planted_spectrum():
+    """10,000 x 20, sigma_j = 10^(-(j-1)/4): planted sigma to 1e-12 relative, U/V vs oracle."""
+    spec = sm.workload_spec(1)
+    A = sm.planted(spec["m"], spec["n"], spec["sigma"], workload=1)
+    flush_print("case workload1", A.shape)
+    U, S, V, info = _run(A)
+    Ur, Sr, Vr, _ = tssvd_ref(A)
+    assert sigma_rel(S, spec["sigma"]) < 1e-12
+    assert sigma_rel(S, Sr) < 1e-12
+    assert np.max(col_sin(U, Ur)) < 1e-9 and np.max(col_sin(V, Vr)) < 1e-9
+    np.testing.assert_allclose(U, Ur, atol=1e-9)
+    np.testing.assert_allclose(V, Vr, atol=1e-9)
+    assert checks.ortho_spec(U) < 1e-13 and checks.ortho_spec(V) < 1e-13
+    assert info["numstat"] == 0 and info["rank"] == 20
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (16, 16), (17, 17), (300, 5), (257, 16), (1000, 17),
+                                 (4099, 33), (5000, 64), (3001, 65), (20000, 100)])
+@pytest.mark.parametrize("ortho", [T.ORTHO_ONCE, T.ORTHO_TWICE])
+def test_shapes_vs_oracle(m, n, ortho):
+    flush_print("case shapes", m, n, ortho)
+    A = _graded(m, n, seed=m * 131 + n)
+    U, S, V, info = _run(A, ortho=ortho)
+    Ur, Sr, Vr, _ = tssvd_ref(A)
+    assert sigma_rel(S, Sr) < 1e-12
+    assert np.max(col_sin(U, Ur)) < 1e-9
+    assert np.max(col_sin(V, Vr)) < 1e-9
+    np.testing.assert_allclose(U, Ur, atol=1e-9)
+    assert checks.ortho_spec(U) < 1e-13 and checks.ortho_spec(V) < 1e-13
+    assert np.all(np.diff(S) <= 0)
+    if ortho == T.ORTHO_TWICE:
+        assert info["reorth"] == 1
+
+
+def test_float32_storage_is_exact_upcast():
+    """A stored in float32: the result is the SVD of the stored values (oracle on the upcast)."""
+    A32 = _graded(6000, 40, seed=5).astype(np.float32)
+    U, S, V, _ = _run(A32.astype(np.float64), dtype=torch.float32)
+    Ur, Sr, Vr, _ = tssvd_ref(A32.astype(np.float64))
+    assert sigma_rel(S, Sr) < 1e-12
+    np.testing.assert_allclose(U, Ur, atol=1e-9)
+
+
+def test_auto_mode_measures_and_skips():
+    """AUTO: Householder U is orthonormal to working precision, so the second pass is skipped."""
+    A = _graded(8000, 30, seed=8)
+    U, S, V, info = _run(A, ortho=T.ORTHO_AUTO)
+    assert 0.0 <= info["ortho"] < 1e-13 and info["reorth"] == 0
+    U2, S2, V2, info2 = _run(A, ortho=T.ORTHO_AUTO, reorth_tol=1e-300)
+    assert info2["reorth"] == 1
+    assert sigma_rel(S2, S) < 1e-13 and np.max(col_sin(U2, U)) < 1e-10
+
+
+def test_rank_deficient_zero_columns():
+    """Exactly rank-deficient input, wp = 0: the nonzero part matches; no NaN."""
+    A = _graded(2000, 12, seed=9)
+    A[:, 3] = 0.0
+    A[:, 7] = 2.0 * A[:, 1]
+    U, S, V, info = _run(A)
+    Ur, Sr, Vr, _ = tssvd_ref(A)
+    assert np.all(np.isfinite(U)) and np.all(np.isfinite(V))
+    assert sigma_rel(S[:10], Sr[:10]) < 1e-12
+    assert S[10] < 1e-14 * S[0] and S[11] < 1e-14 * S[0]
+    assert info["numstat"] == 0
+
+
+def test_discard_rule_matches_oracle():
+    """Working precision 1e-11: rows of R below wp |R_11| dropped, same rank as the oracle."""
+    sigma = np.concatenate([np.logspace(0, -5, 9), np.full(3, 1e-15)])
+    A = sm.planted(3000, 12, sigma, workload=41)
+    U, S, V, info = _run(A, working_precision=1e-11)
+    Ur, Sr, Vr, r = tssvd_ref(A, wp=1e-11, double=False)
+    assert info["rank"] == r == 9
+    assert sigma_rel(S[:r], Sr[:r]) < 1e-11
+    assert np.all(S[r:] == 0) and np.all(U[:, r:] == 0) and np.all(V[:, r:] == 0)
+    assert checks.ortho_spec(U, r) < 1e-13
+
+
+def test_deterministic_bitwise():
+    A = _graded(50000, 48, seed=11)
+    a = _run(A)
+    b = _run(A)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("m,n", [(128, 128), (5000, 7), (70001, 100)])
+def test_tsqr_factor_vs_householder(m, n):
+    """R equals LAPACK's Householder R up to row signs; Q R = A; Q^T Q = I."""
+    flush_print("case tsqr", m, n)
+    A = _graded(m, n, seed=m + n)
+    Q, R = T.tsqr(dev(A))
+    torch.cuda.synchronize()
+    Q, R = host(Q), host(R)
+    _, Rn = np.linalg.qr(A)
+    d = np.sign(np.diag(R)) * np.sign(np.diag(Rn))
+    np.testing.assert_allclose(R * d[:, None], Rn, atol=1e-12 * np.abs(Rn).max())
+    assert np.all(np.tril(R, -1) == 0)
+    np.testing.assert_allclose(Q @ R, A, atol=1e-12 * np.abs(A).max())
+    assert checks.ortho_spec(Q) < 1e-13
+
+
+def test_tsqr_float32_input():
+    A32 = _graded(9000, 20, seed=3).astype(np.float32)
+    Q, R = T.tsqr(dev(A32))
+    torch.cuda.synchronize()
+    Q, R = host(Q), host(R)
+    np.testing.assert_allclose(Q @ R, A32.astype(np.float64), atol=1e-12)
