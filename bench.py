@@ -172,6 +172,9 @@ def main():
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--legs", default="w1,w3")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB read + 1 GiB write elementwise kernel first (counter "
+                         "calibration for the HBM traffic figures)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -181,6 +184,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     head = leg_lowrank(args.workload, args.steps, args.warmup, not args.no_cpu)
     spec = head["spec"]
     legs = {}
