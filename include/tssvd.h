@@ -177,11 +177,15 @@ int lowrank_svd_backward(const void* A, int32_t a_dtype, int64_t m, int64_t n, i
  * created on first use and reused; no device memory is allocated.
  * ------------------------------------------------------------------------------------- */
 enum {
-  TSSVD_PROF_AX = 0,           /* Y = A X passes over A                                   */
-  TSSVD_PROF_ATQ = 1,          /* Z = A^T Q passes over A (main kernel, before the reduce) */
+  TSSVD_PROF_AX = 0,           /* Y = A X passes over A, float64 products                 */
+  TSSVD_PROF_ATQ = 1,          /* Z = A^T Q passes over A, float64 (before the reduce)    */
   TSSVD_PROF_LEAF_FACTOR = 2,  /* TSQR leaf factorization (reads the tall matrix)         */
   TSSVD_PROF_LEAF_APPLY = 3,   /* TSQR leaf application (writes the tall factor)          */
-  TSSVD_PROF_KINDS = 4
+  TSSVD_PROF_AX_BF16 = 4,      /* Y = A X, bfloat16 inputs (mixed power steps)            */
+  TSSVD_PROF_ATQ_BF16 = 5,     /* Z = A^T Q, bfloat16 inputs (mixed power steps)          */
+  TSSVD_PROF_AX_F32 = 6,       /* Y = A X, float32 inputs (mixed final sketch)            */
+  TSSVD_PROF_ATQ_F32 = 7,      /* Z = A^T Q, float32 inputs (mixed B = Q^T A)             */
+  TSSVD_PROF_KINDS = 8
 };
 int tssvd_profile_enable(int on);      /* on != 0: start recording (counters reset)      */
 int tssvd_profile_read(int kind, double* total_ms, int64_t* launches);

@@ -31,6 +31,9 @@ EXPORTS = (
 )
 
 PROF_AX, PROF_ATQ, PROF_LEAF_FACTOR, PROF_LEAF_APPLY = 0, 1, 2, 3
+PROF_AX_BF16, PROF_ATQ_BF16, PROF_AX_F32, PROF_ATQ_F32 = 4, 5, 6, 7
+PROF_NAMES = {0: "gemm_ax_f64", 1: "gemm_atq_f64", 2: "tsqr_leaf_factor", 3: "tsqr_leaf_apply",
+              4: "ax_bf16", 5: "atq_bf16", 6: "ax_f32", 7: "atq_f32"}
 
 
 class Opts(C.Structure):

@@ -250,11 +250,12 @@ namespace {
 struct LowrankWs {
   TsqrPlan pY, pZ;
   double *X, *Y, *Z, *part, *I, *P, *sig, *W, *Wk, *G, *ortho, *Tq;
+  void* pack;
   int* gate;
   size_t bytes;
 };
 
-LowrankWs lowrank_layout(int64_t m, int64_t n, int k, int l, void* work) {
+LowrankWs lowrank_layout(int64_t m, int64_t n, int k, int l, void* work, bool mixed) {
   LowrankWs w;
   Carver c(work);
   w.pY = tsqr_plan(m, l);
@@ -267,7 +268,14 @@ LowrankWs lowrank_layout(int64_t m, int64_t n, int k, int l, void* work) {
   size_t np = atq_partials(m, n, l);
   const size_t np2 = atq_partials(m, l, l);
   if (np2 > np) np = np2;
+  if (mixed && mixed_partials(m, n, l) > np) np = mixed_partials(m, n, l);
   w.part = c.take<double>(np);
+  w.pack = nullptr;
+  if (mixed) {
+    size_t pb = mixed_pack_bytes(m, l);
+    if (mixed_pack_bytes(n, l) > pb) pb = mixed_pack_bytes(n, l);
+    w.pack = c.take<char>(pb);
+  }
   const size_t ll = (size_t)l * l;
   w.I = c.take<double>(ll);
   w.P = c.take<double>(ll);
@@ -307,7 +315,8 @@ int lowrank_svd_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t l, int6
   int st = lowrank_check((const void*)1, a_dtype, m, n, n, k, l, q);
   if (st != TSSVD_OK) return st;
   (void)opts;
-  *bytes = lowrank_layout(m, n, (int)k, (int)l, nullptr).bytes;
+  const bool mixed = opts && opts->prec == TSSVD_PREC_MIXED;
+  *bytes = lowrank_layout(m, n, (int)k, (int)l, nullptr, mixed).bytes;
   return TSSVD_OK;
 }
 
@@ -320,10 +329,11 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   if (!U || !S || !V || ldu < k || ldv < k) return TSSVD_E_INVALID_ARG;
   const tssvd_opts o = resolve(opts);
   if (check_opts(o) != TSSVD_OK) return TSSVD_E_INVALID_ARG;
-  if (o.prec != TSSVD_PREC_FP64) return TSSVD_E_UNSUPPORTED;
+  const bool mixed = o.prec == TSSVD_PREC_MIXED;
+  if (mixed && a_dtype != TSSVD_F32) return TSSVD_E_INVALID_ARG;
   if (o.working_precision > 0.0) return TSSVD_E_UNSUPPORTED;
   const int ki = (int)k, li = (int)l;
-  LowrankWs w = lowrank_layout(m, n, ki, li, work);
+  LowrankWs w = lowrank_layout(m, n, ki, li, work, mixed);
   if (!work || work_bytes < w.bytes) return TSSVD_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
 
@@ -333,14 +343,33 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
     TRY(copy_matrix(Omega, n, li, l, w.X, l, s));
   else
     TRY(philox_sketch(w.X, n, li, o.seed, s));
+  // Products with A.  FP64: float64 MFMA on A as stored.  MIXED: bfloat16 inputs in the
+  // power steps, float32 inputs for the last sketch and for B (the operand is packed first).
+  const float* A32 = static_cast<const float*>(A);
+  auto ax = [&](const double* Xs, bool last) -> hipError_t {
+    if (!mixed) return gemm_ax_f64(A, a_dtype, lda, m, n, Xs, li, li, w.Y, li, s, TSSVD_PROF_AX);
+    const int kind = last ? MIX_F32_AX : MIX_BF16;
+    hipError_t e = pack_operand(Xs, n, li, li, kind, w.pack, s);
+    if (e != hipSuccess) return e;
+    return gemm_ax_mixed(A32, lda, m, n, w.pack, li, w.Y, li, kind, s,
+                         last ? TSSVD_PROF_AX_F32 : TSSVD_PROF_AX_BF16);
+  };
+  auto atq = [&](bool last) -> hipError_t {
+    if (!mixed)
+      return gemm_atq_f64(A, a_dtype, lda, m, n, w.Y, li, li, w.Z, li, w.part, s, TSSVD_PROF_ATQ);
+    const int kind = last ? MIX_F32_ROWS : MIX_BF16;
+    hipError_t e = pack_operand(w.Y, m, li, li, kind, w.pack, s);
+    if (e != hipSuccess) return e;
+    return gemm_atq_mixed(A32, lda, m, n, w.pack, li, w.Z, li, w.part, kind, s,
+                          last ? TSSVD_PROF_ATQ_F32 : TSSVD_PROF_ATQ_BF16);
+  };
   // Algorithm 5: subspace iteration
-  TRY(gemm_ax_f64(A, a_dtype, lda, m, n, w.X, li, li, w.Y, li, s, TSSVD_PROF_AX));  // A Q~_0
+  TRY(ax(w.X, q == 0));                                                        // A Q~_0
   for (int64_t j = 0; j < q; ++j) {
     TRY(orth_inplace(w.pY, w.Y, li, w.I, s));                                  // Q_j
-    TRY(gemm_atq_f64(A, a_dtype, lda, m, n, w.Y, li, li, w.Z, li, w.part, s,
-                     TSSVD_PROF_ATQ));                                         // A^* Q_j
+    TRY(atq(false));                                                           // A^* Q_j
     TRY(orth_inplace(w.pZ, w.Z, li, w.I, s));                                  // Q~_j
-    TRY(gemm_ax_f64(A, a_dtype, lda, m, n, w.Z, li, li, w.Y, li, s, TSSVD_PROF_AX));  // A Q~_j
+    TRY(ax(w.Z, j == q - 1));                                                  // A Q~_j
   }
   TRY(orth_inplace(w.pY, w.Y, li, w.I, s));                                    // Q
   if (o.ortho != TSSVD_ORTHO_ONCE) {
@@ -355,7 +384,7 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   }
   // Algorithm 6: B = Q^* A via B^* = A^* Q = Q_B R_B;  R_B^T = P S W^T  =>
   //   B = P S (Q_B W)^T,  U = Q P_k,  V = Q_B W_k.
-  TRY(gemm_atq_f64(A, a_dtype, lda, m, n, w.Y, li, li, w.Z, li, w.part, s, TSSVD_PROF_ATQ));
+  TRY(atq(true));                                                              // B^* = A^* Q
   TRY(tsqr_factor(w.pZ, w.Z, TSSVD_F64, l, s));
   TRY(jacobi_svd(tsqr_root(w.pZ), li, li, 1, 0.0, o.max_jacobi_sweeps, 0, w.P, w.sig, w.W,
                  info, s));

@@ -256,6 +256,11 @@ hipError_t gemm_atq_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int6
   int ncol, nchunk;
   int64_t cr;
   atq_grid(m, n, ncol, nchunk, cr);
+  return reduce_chunks(part, nchunk, n, l, Z, ldz, s);
+}
+
+hipError_t reduce_chunks(const double* part, int nchunk, int64_t n, int l, double* Z, int ldz,
+                         hipStream_t s) {
   const int64_t count = n * (int64_t)l;
   hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
                      part, nchunk, count, Z, l, ldz);

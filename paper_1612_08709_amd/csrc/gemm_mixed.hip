@@ -1,0 +1,472 @@
+// Mixed-precision products with a float32-stored A on gfx950 matrix cores.
+//
+//   power steps (Algorithm 5 steps 2, 5 and 7 before the last):  bfloat16 inputs (round to
+//   nearest even, converted in registers), float32 accumulation, v_mfma_f32_16x16x32_bf16;
+//   final sketch (Algorithm 5 step 9) and B^* = A^* Q (Algorithm 6 step 1): float32 inputs
+//   and accumulation, v_mfma_f32_16x16x4_f32.
+// Results are written in float64; A^T Q partials over row chunks are reduced in float64 in
+// chunk order (same reduction kernel as the float64 path).
+//
+// Operand layouts (measured on gfx950):
+//   16x16x32 bf16: A operand lane l holds row l%16, k = 8*(l/16) + e (e < 8); B operand
+//                  column l%16, k = 8*(l/16) + e; result register r = D[4*(l/16)+r][l%16].
+//   16x16x4 f32:   A operand row l%16, k = l/16; B operand k = l/16, column l%16;
+//                  result register r = D[4*(l/16)+r][l%16].
+// A is read straight into fragments: for Y = A X a lane reads 8 (bf16) or 4 (f32)
+// consecutive columns of one row; for Z = A^T Q a lane reads 4 consecutive columns of 8
+// (bf16) or 1 (f32) rows and the four result tiles interleave those columns (tile e holds
+// columns c + 4i + e), so no transposition through shared memory is needed.  The small
+// operand (X or Q) is packed beforehand into the exact per-lane fragment order.
+#include "common.h"
+#include "internal.h"
+
+namespace tsv {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- operand packing
+// bf16 B-operand fragments of a K x l float64 matrix S (stride lds):
+//   P[(kb*NT + nt)*64 + lane][e] = S[32 kb + 8 (lane/16) + e][16 nt + lane%16]  (0 outside)
+__global__ void k_pack_bf16(const double* __restrict__ S, int64_t K, int l, int lds, int NT,
+                            int64_t nkb, bf16x8* __restrict__ P) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nkb * NT * 64) return;
+  const int lane = (int)(idx & 63);
+  const int64_t t = idx >> 6;
+  const int nt = (int)(t % NT);
+  const int64_t kb = t / NT;
+  const int col = 16 * nt + (lane & 15);
+  const int64_t k0 = 32 * kb + 8 * (lane >> 4);
+  bf16x8 v;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t k = k0 + e;
+    v[e] = (__bf16)((k < K && col < l) ? (float)S[k * lds + col] : 0.0f);
+  }
+  P[idx] = v;
+}
+
+// f32 B-operand fragments for Y = A X:  P[((kb*NT + nt)*64 + lane)*4 + s] =
+//   S[16 kb + 4 (lane/16) + s][16 nt + lane%16]
+__global__ void k_pack_f32_ax(const double* __restrict__ S, int64_t K, int l, int lds, int NT,
+                              int64_t nkb, float* __restrict__ P) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nkb * NT * 64) return;
+  const int lane = (int)(idx & 63);
+  const int64_t t = idx >> 6;
+  const int nt = (int)(t % NT);
+  const int64_t kb = t / NT;
+  const int col = 16 * nt + (lane & 15);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int64_t k = 16 * kb + 4 * (lane >> 4) + s;
+    P[idx * 4 + s] = (k < K && col < l) ? (float)S[k * lds + col] : 0.0f;
+  }
+}
+
+// f32 rows of Q padded to L = 16 NT columns and to whole row quads: P[r*L + c]
+__global__ void k_pack_f32_rows(const double* __restrict__ S, int64_t K, int l, int lds, int L,
+                                int64_t Kpad, float* __restrict__ P) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= Kpad * L) return;
+  const int64_t r = idx / L;
+  const int c = (int)(idx - r * L);
+  P[idx] = (r < K && c < l) ? (float)S[r * lds + c] : 0.0f;
+}
+
+__device__ __forceinline__ bool aligned16(const void* p) {
+  return (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+}
+
+// ---------------------------------------------------------------- Y = A X, bf16
+template <int RT, int NT>
+__global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, int64_t lda,
+                                                 int64_t m, int n,
+                                                 const bf16x8* __restrict__ Xp, int l,
+                                                 double* __restrict__ Y, int ldy) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t rbase = (int64_t)blockIdx.x * (64 * RT) + (int64_t)wave * (16 * RT);
+  f32x4 acc[RT][NT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const float* arow[RT];
+  bool rok[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int64_t row = rbase + 16 * rt + li;
+    rok[rt] = row < m;
+    arow[rt] = A + (rok[rt] ? row : 0) * lda;
+  }
+  const int nkb = (n + 31) / 32;
+  for (int kb = 0; kb < nkb; ++kb) {
+    const int k0 = 32 * kb + 8 * g;
+    bf16x8 a[RT], b[NT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      float v[8];
+      const float* p = arow[rt] + k0;
+      if (rok[rt] && k0 + 8 <= n && aligned16(p)) {
+        const float4 x0 = *reinterpret_cast<const float4*>(p);
+        const float4 x1 = *reinterpret_cast<const float4*>(p + 4);
+        v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
+        v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (rok[rt] && k0 + e < n) ? p[e] : 0.0f;
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) a[rt][e] = (__bf16)v[e];
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) b[nt] = Xp[((int64_t)kb * NT + nt) * 64 + lane];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mfma_bf16(a[rt], b[nt], acc[rt][nt]);
+  }
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int col = 16 * nt + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = rbase + 16 * rt + 4 * g + r;
+        if (row < m && col < l) Y[row * ldy + col] = (double)acc[rt][nt][r];
+      }
+    }
+}
+
+// ---------------------------------------------------------------- Y = A X, f32
+template <int RT, int NT>
+__global__ __launch_bounds__(256) void k_ax_f32(const float* __restrict__ A, int64_t lda,
+                                                int64_t m, int n, const float* __restrict__ Xp,
+                                                int l, double* __restrict__ Y, int ldy) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t rbase = (int64_t)blockIdx.x * (64 * RT) + (int64_t)wave * (16 * RT);
+  f32x4 acc[RT][NT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const float* arow[RT];
+  bool rok[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int64_t row = rbase + 16 * rt + li;
+    rok[rt] = row < m;
+    arow[rt] = A + (rok[rt] ? row : 0) * lda;
+  }
+  const int nkb = (n + 15) / 16;
+  for (int kb = 0; kb < nkb; ++kb) {
+    const int k0 = 16 * kb + 4 * g;
+    float a[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const float* p = arow[rt] + k0;
+      if (rok[rt] && k0 + 4 <= n && aligned16(p)) {
+        const float4 x = *reinterpret_cast<const float4*>(p);
+        a[rt][0] = x.x; a[rt][1] = x.y; a[rt][2] = x.z; a[rt][3] = x.w;
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[rt][s] = (rok[rt] && k0 + s < n) ? p[s] : 0.0f;
+      }
+    }
+    float4 b[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+      b[nt] = reinterpret_cast<const float4*>(Xp)[((int64_t)kb * NT + nt) * 64 + lane];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        acc[rt][nt] = mfma_f32(a[rt][0], b[nt].x, acc[rt][nt]);
+        acc[rt][nt] = mfma_f32(a[rt][1], b[nt].y, acc[rt][nt]);
+        acc[rt][nt] = mfma_f32(a[rt][2], b[nt].z, acc[rt][nt]);
+        acc[rt][nt] = mfma_f32(a[rt][3], b[nt].w, acc[rt][nt]);
+      }
+  }
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int col = 16 * nt + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = rbase + 16 * rt + 4 * g + r;
+        if (row < m && col < l) Y[row * ldy + col] = (double)acc[rt][nt][r];
+      }
+    }
+}
+
+// ---------------------------------------------------------------- Z = A^T Q, bf16 / f32
+// Workgroup = (row chunk, 256-column tile), wave w owns 64 columns cw = c0 + 64 w.
+constexpr int MX_COLS = 256;
+
+__device__ __forceinline__ void mx_tile(int total, int ncol, int& chunk, int& ct, bool& ok) {
+  const int per = (total + 7) / 8;
+  const int L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  ok = L < total;
+  chunk = ok ? L / ncol : 0;
+  ct = ok ? L - chunk * ncol : 0;
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_atq_bf16(const float* __restrict__ A, int64_t lda,
+                                                  int64_t m, int n,
+                                                  const bf16x8* __restrict__ Qp, int l,
+                                                  int ncol, int nchunk, int64_t chunk_rows,
+                                                  double* __restrict__ part) {
+  int chunk, ct;
+  bool ok;
+  mx_tile(ncol * nchunk, ncol, chunk, ct, ok);
+  if (!ok) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int cw = ct * MX_COLS + 64 * wave;
+  if (cw >= n) return;
+  const int64_t r0 = (int64_t)chunk * chunk_rows;  // chunk_rows is a multiple of 32
+  const int64_t r1 = (r0 + chunk_rows < m) ? r0 + chunk_rows : m;
+  const int cb = cw + 4 * li;
+  const bool cvec = (cb + 4 <= n);
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[e][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t rb = r0; rb < r1; rb += 32) {
+    bf16x8 a[4];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t row = rb + 8 * g + t;
+      const float* p = A + row * lda + cb;
+      float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f;
+      if (row < r1) {
+        if (cvec && aligned16(p)) {
+          const float4 x = *reinterpret_cast<const float4*>(p);
+          v0 = x.x; v1 = x.y; v2 = x.z; v3 = x.w;
+        } else {
+          v0 = (cb + 0 < n) ? p[0] : 0.f;
+          v1 = (cb + 1 < n) ? p[1] : 0.f;
+          v2 = (cb + 2 < n) ? p[2] : 0.f;
+          v3 = (cb + 3 < n) ? p[3] : 0.f;
+        }
+      }
+      a[0][t] = (__bf16)v0;
+      a[1][t] = (__bf16)v1;
+      a[2][t] = (__bf16)v2;
+      a[3][t] = (__bf16)v3;
+    }
+    const int64_t kb = rb >> 5;
+    bf16x8 b[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) b[nt] = Qp[(kb * NT + nt) * 64 + lane];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[e][nt] = mfma_bf16(a[e], b[nt], acc[e][nt]);
+  }
+  double* P = part + (int64_t)chunk * n * l;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int col = 16 * nt + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = cw + 4 * (4 * g + r) + e;
+        if (c < n && col < l) P[(int64_t)c * l + col] = (double)acc[e][nt][r];
+      }
+    }
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_atq_f32(const float* __restrict__ A, int64_t lda,
+                                                 int64_t m, int n, const float* __restrict__ Qf,
+                                                 int l, int ncol, int nchunk,
+                                                 int64_t chunk_rows, double* __restrict__ part) {
+  int chunk, ct;
+  bool ok;
+  mx_tile(ncol * nchunk, ncol, chunk, ct, ok);
+  if (!ok) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int cw = ct * MX_COLS + 64 * wave;
+  if (cw >= n) return;
+  constexpr int L = 16 * NT;
+  const int64_t r0 = (int64_t)chunk * chunk_rows;
+  const int64_t r1 = (r0 + chunk_rows < m) ? r0 + chunk_rows : m;
+  const int cb = cw + 4 * li;
+  const bool cvec = (cb + 4 <= n);
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[e][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t rq = r0; rq < r1; rq += 4) {
+    const int64_t row = rq + g;
+    const float* p = A + row * lda + cb;
+    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f;
+    if (row < r1) {
+      if (cvec && aligned16(p)) {
+        const float4 x = *reinterpret_cast<const float4*>(p);
+        v0 = x.x; v1 = x.y; v2 = x.z; v3 = x.w;
+      } else {
+        v0 = (cb + 0 < n) ? p[0] : 0.f;
+        v1 = (cb + 1 < n) ? p[1] : 0.f;
+        v2 = (cb + 2 < n) ? p[2] : 0.f;
+        v3 = (cb + 3 < n) ? p[3] : 0.f;
+      }
+    }
+    float b[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) b[nt] = Qf[row * L + 16 * nt + li];  // rows padded
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      acc[0][nt] = mfma_f32(v0, b[nt], acc[0][nt]);
+      acc[1][nt] = mfma_f32(v1, b[nt], acc[1][nt]);
+      acc[2][nt] = mfma_f32(v2, b[nt], acc[2][nt]);
+      acc[3][nt] = mfma_f32(v3, b[nt], acc[3][nt]);
+    }
+  }
+  double* P = part + (int64_t)chunk * n * l;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int col = 16 * nt + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = cw + 4 * (4 * g + r) + e;
+        if (c < n && col < l) P[(int64_t)c * l + col] = (double)acc[e][nt][r];
+      }
+    }
+}
+
+// ---------------------------------------------------------------- host side
+static void mx_grid(int64_t m, int64_t n, int& ncol, int& nchunk, int64_t& chunk_rows) {
+  ncol = (int)((n + MX_COLS - 1) / MX_COLS);
+  int64_t want = (1024 + ncol - 1) / ncol;
+  const int64_t maxc = (m + 255) / 256;
+  if (want > maxc) want = maxc;
+  if (want < 1) want = 1;
+  chunk_rows = (m + want - 1) / want;
+  chunk_rows = (chunk_rows + 31) / 32 * 32;
+  nchunk = (int)((m + chunk_rows - 1) / chunk_rows);
+}
+
+size_t mixed_partials(int64_t m, int64_t n, int l) {
+  int ncol, nchunk;
+  int64_t cr;
+  mx_grid(m, n, ncol, nchunk, cr);
+  return (size_t)nchunk * n * l;
+}
+
+size_t mixed_pack_bytes(int64_t K, int l) {
+  const int NT = (l + 15) / 16;
+  const int64_t Kpad = (K + 31) / 32 * 32;
+  return (size_t)Kpad * 16 * NT * 4;  // the largest of the three packings (f32, padded)
+}
+
+hipError_t pack_operand(const double* S, int64_t K, int l, int lds, int kind, void* P,
+                        hipStream_t s) {
+  const int NT = (l + 15) / 16;
+  if (kind == MIX_BF16) {
+    const int64_t nkb = (K + 31) / 32;
+    const int64_t tot = nkb * NT * 64;
+    hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, S, K,
+                       l, lds, NT, nkb, (bf16x8*)P);
+  } else if (kind == MIX_F32_AX) {
+    const int64_t nkb = (K + 15) / 16;
+    const int64_t tot = nkb * NT * 64;
+    hipLaunchKernelGGL(k_pack_f32_ax, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, S,
+                       K, l, lds, NT, nkb, (float*)P);
+  } else {
+    const int64_t Kpad = (K + 31) / 32 * 32;
+    const int64_t tot = Kpad * 16 * NT;
+    hipLaunchKernelGGL(k_pack_f32_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, S,
+                       K, l, lds, 16 * NT, Kpad, (float*)P);
+  }
+  return hipGetLastError();
+}
+
+template <int NT>
+static void launch_ax_mixed(const float* A, int64_t lda, int64_t m, int64_t n, const void* Xp,
+                            int l, double* Y, int ldy, int kind, hipStream_t s) {
+  constexpr int RT = 2;
+  const unsigned grid = (unsigned)((m + 64 * RT - 1) / (64 * RT));
+  if (kind == MIX_BF16)
+    hipLaunchKernelGGL((k_ax_bf16<RT, NT>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
+                       (const bf16x8*)Xp, l, Y, ldy);
+  else
+    hipLaunchKernelGGL((k_ax_f32<RT, NT>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
+                       (const float*)Xp, l, Y, ldy);
+}
+
+hipError_t gemm_ax_mixed(const float* A, int64_t lda, int64_t m, int64_t n, const void* Xp,
+                         int l, double* Y, int ldy, int kind, hipStream_t s, int prof) {
+  prof_begin(prof, s);
+  switch ((l + 15) / 16) {
+    case 1: launch_ax_mixed<1>(A, lda, m, n, Xp, l, Y, ldy, kind, s); break;
+    case 2: launch_ax_mixed<2>(A, lda, m, n, Xp, l, Y, ldy, kind, s); break;
+    case 3: launch_ax_mixed<3>(A, lda, m, n, Xp, l, Y, ldy, kind, s); break;
+    case 4: launch_ax_mixed<4>(A, lda, m, n, Xp, l, Y, ldy, kind, s); break;
+    case 5: launch_ax_mixed<5>(A, lda, m, n, Xp, l, Y, ldy, kind, s); break;
+    case 6: launch_ax_mixed<6>(A, lda, m, n, Xp, l, Y, ldy, kind, s); break;
+    case 7: launch_ax_mixed<7>(A, lda, m, n, Xp, l, Y, ldy, kind, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  prof_end(prof, s);
+  return hipGetLastError();
+}
+
+template <int NT>
+static void launch_atq_mixed(const float* A, int64_t lda, int64_t m, int64_t n, const void* Qp,
+                             int l, double* part, int kind, hipStream_t s) {
+  int ncol, nchunk;
+  int64_t cr;
+  mx_grid(m, n, ncol, nchunk, cr);
+  const int total = ncol * nchunk;
+  const int grid = ((total + 7) / 8) * 8;
+  if (kind == MIX_BF16)
+    hipLaunchKernelGGL((k_atq_bf16<NT>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
+                       (const bf16x8*)Qp, l, ncol, nchunk, cr, part);
+  else
+    hipLaunchKernelGGL((k_atq_f32<NT>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
+                       (const float*)Qp, l, ncol, nchunk, cr, part);
+}
+
+hipError_t gemm_atq_mixed(const float* A, int64_t lda, int64_t m, int64_t n, const void* Qp,
+                          int l, double* Z, int ldz, double* part, int kind, hipStream_t s,
+                          int prof) {
+  prof_begin(prof, s);
+  switch ((l + 15) / 16) {
+    case 1: launch_atq_mixed<1>(A, lda, m, n, Qp, l, part, kind, s); break;
+    case 2: launch_atq_mixed<2>(A, lda, m, n, Qp, l, part, kind, s); break;
+    case 3: launch_atq_mixed<3>(A, lda, m, n, Qp, l, part, kind, s); break;
+    case 4: launch_atq_mixed<4>(A, lda, m, n, Qp, l, part, kind, s); break;
+    case 5: launch_atq_mixed<5>(A, lda, m, n, Qp, l, part, kind, s); break;
+    case 6: launch_atq_mixed<6>(A, lda, m, n, Qp, l, part, kind, s); break;
+    case 7: launch_atq_mixed<7>(A, lda, m, n, Qp, l, part, kind, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  prof_end(prof, s);
+  int ncol, nchunk;
+  int64_t cr;
+  mx_grid(m, n, ncol, nchunk, cr);
+  return reduce_chunks(part, nchunk, n, l, Z, ldz, s);
+}
+
+}  // namespace tsv

@@ -79,6 +79,27 @@ hipError_t gemm_atq_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int6
                         const double* Q, int ldq, int l, double* Z, int ldz, double* part,
                         hipStream_t s, int prof = -1);
 
+hipError_t reduce_chunks(const double* part, int nchunk, int64_t n, int l, double* Z, int ldz,
+                         hipStream_t s);
+
+// Mixed precision (A stored float32).  kind: operand packing / MFMA flavour.
+constexpr int MIX_BF16 = 0;    // bfloat16 inputs, float32 accumulation
+constexpr int MIX_F32_AX = 1;  // float32 inputs, packed for Y = A X
+constexpr int MIX_F32_ROWS = 2;  // float32 inputs, padded rows for Z = A^T Q
+size_t mixed_partials(int64_t m, int64_t n, int l);
+size_t mixed_pack_bytes(int64_t K, int l);
+// Pack the K x l float64 operand S (stride lds) for the kernels below.
+hipError_t pack_operand(const double* S, int64_t K, int l, int lds, int kind, void* P,
+                        hipStream_t s);
+// Y (m x l) = A X with X packed as MIX_BF16 or MIX_F32_AX.
+hipError_t gemm_ax_mixed(const float* A, int64_t lda, int64_t m, int64_t n, const void* Xp,
+                         int l, double* Y, int ldy, int kind, hipStream_t s, int prof = -1);
+// Z (n x l) = A^T Q with Q packed as MIX_BF16 or MIX_F32_ROWS (kind MIX_F32_ROWS selects
+// the float32 kernel).
+hipError_t gemm_atq_mixed(const float* A, int64_t lda, int64_t m, int64_t n, const void* Qp,
+                          int l, double* Z, int ldz, double* part, int kind, hipStream_t s,
+                          int prof = -1);
+
 // ------------------------------------------------------------------ misc
 hipError_t fill_identity(double* S, int n, int k, hipStream_t s);
 hipError_t philox_sketch(double* X, int64_t n, int l, uint64_t seed, hipStream_t s);

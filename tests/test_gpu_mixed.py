@@ -1,0 +1,79 @@
+"""GPU parity of the mixed-precision randomized SVD (A stored float32).
+
+Power-step products take bfloat16 inputs, the final sketch and B = Q^T A take float32
+inputs; TSQR, the small SVD and the orthonormalization stay float64.  The reference is the
+float64 oracle on the exactly upcast float32 matrix with the same sketch.  Gates: the
+orthonormality of U and V (<= 1e-12, spectral norm) and the spectral residual
+||A - U S V^T||_2 within 1e-6 (relative to sigma_1) of the oracle's.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import checks
+from oracle.lowrank_ref import lowrank_ref
+from synth import matrices as sm
+
+from gpu_util import col_sin, dev, flush_print, host, sigma_rel
+
+pytestmark = pytest.mark.gpu
+
+T = pytest.importorskip("paper_1612_08709_amd")
+
+
+def _workload4_like(m, n, workload, r=None):
+    sigma = np.exp(-np.arange(1, (r or min(m, n)) + 1) / 15.0)
+    return sm.planted(m, n, sigma, workload=workload, noise=1e-5).astype(np.float32), sigma
+
+
+def _run_mixed(A32, Om, k, q, prec):
+    U, S, V, info = T.lowrank_svd(dev(A32), k, Om.shape[1], q, dev(Om), prec=prec)
+    torch.cuda.synchronize()
+    return host(U), host(S), host(V), info
+
+
+@pytest.mark.parametrize("m,n,k,l,q", [(20000, 1500, 50, 60, 3), (3001, 517, 16, 24, 2),
+                                       (5000, 640, 10, 30, 0), (4099, 333, 8, 12, 1)])
+def test_mixed_vs_oracle_on_upcast(m, n, k, l, q):
+    flush_print("case mixed", m, n, k, l, q)
+    A32, _ = _workload4_like(m, n, 70 + l, r=min(m, n, 300))
+    Om = sm.sketch(n, l, 70 + l)
+    U, S, V, info = _run_mixed(A32, Om, k, q, T.PREC_MIXED)
+    A64 = A32.astype(np.float64)
+    Ur, Sr, Vr = lowrank_ref(A64, Om, k, q)
+    assert checks.ortho_spec(U) <= 1e-12 and checks.ortho_spec(V) <= 1e-12
+    e = checks.spectral_residual(A64, U, S, V, tol=1e-9)
+    er = checks.spectral_residual(A64, Ur, Sr, Vr, tol=1e-9)
+    flush_print(f"  residual mixed {e:.6e} oracle {er:.6e} diff {abs(e - er):.2e}; "
+                f"sigma rel {sigma_rel(S, Sr):.2e}")
+    assert abs(e - er) <= 1e-6 * Sr[0]
+    assert sigma_rel(S, Sr) < 1e-3
+
+
+def test_mixed_matches_fp64_gpu_path():
+    """Same float32 A and sketch: mixed vs the all-float64 GPU path, residual within 1e-6."""
+    A32, _ = _workload4_like(30000, 2000, 75, r=400)
+    Om = sm.sketch(2000, 60, 75)
+    Um, Sm, Vm, _ = _run_mixed(A32, Om, 50, 3, T.PREC_MIXED)
+    Uf, Sf, Vf, _ = _run_mixed(A32, Om, 50, 3, T.PREC_FP64)
+    A64 = A32.astype(np.float64)
+    em = checks.spectral_residual(A64, Um, Sm, Vm, tol=1e-9)
+    ef = checks.spectral_residual(A64, Uf, Sf, Vf, tol=1e-9)
+    assert abs(em - ef) <= 1e-6 * Sf[0]
+    assert checks.ortho_spec(Um) <= 1e-12 and checks.ortho_spec(Uf) <= 1e-13
+
+
+def test_mixed_requires_float32_storage():
+    A = torch.zeros(1000, 100, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(ValueError):
+        T.lowrank_svd(A, 4, 8, 1, None, prec=T.PREC_MIXED)
+
+
+def test_mixed_deterministic_bitwise():
+    A32, _ = _workload4_like(8000, 700, 76, r=200)
+    Om = dev(sm.sketch(700, 30, 76))
+    Ad = dev(A32)
+    r1 = [host(x) for x in T.lowrank_svd(Ad, 20, 30, 2, Om, prec=T.PREC_MIXED)[:3]]
+    r2 = [host(x) for x in T.lowrank_svd(Ad, 20, 30, 2, Om, prec=T.PREC_MIXED)[:3]]
+    for a, b in zip(r1, r2):
+        assert np.array_equal(a, b)
