@@ -74,9 +74,11 @@ def kernel_model(name, m, n, l, a_bytes_per_elem):
     if name in ("ax_bf16", "atq_bf16"):
         return dict(alg_bytes=abytes + 2 * (m * l if "atq" in name else n * l) +
                     8 * (n * l if "atq" in name else m * l), flops=2.0 * m * n * L, dtype="bf16")
-    if name in ("ax_f32", "atq_f32"):
+    if name in ("ax_final", "atq_final"):
+        # float32-exact inputs as three bfloat16 pieces: six bf16 products per MFMA tile
         return dict(alg_bytes=abytes + 4 * (m * l if "atq" in name else n * l) +
-                    8 * (n * l if "atq" in name else m * l), flops=2.0 * m * n * L, dtype="f32")
+                    8 * (n * l if "atq" in name else m * l), flops=6 * 2.0 * m * n * L,
+                    dtype="bf16")
     return None
 
 

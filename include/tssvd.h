@@ -59,10 +59,11 @@ typedef enum { TSSVD_F64 = 0, TSSVD_F32 = 1 } tssvd_dtype;
 typedef enum {
   TSSVD_PREC_FP64 = 0,       /* every product and factorization in float64              */
   TSSVD_PREC_MIXED = 1       /* lowrank_svd: power-iteration products in bfloat16 with
-                                float32 accumulation, final sketch and B products with
-                                float32 inputs and accumulation; TSQR, small SVD and the
-                                second orthonormalization in float64.  Requires a_dtype
-                                == TSSVD_F32.  tssvd: A is read as stored, all arithmetic
+                                float32 accumulation; final sketch and B products with
+                                float32-exact inputs (three bfloat16 pieces per value) and
+                                float32 accumulation; TSQR, small SVD and the second
+                                orthonormalization in float64.  Requires a_dtype ==
+                                TSSVD_F32.  tssvd: A is read as stored, all arithmetic
                                 float64.                                                */
 } tssvd_prec;
 
@@ -80,9 +81,14 @@ typedef struct {
                                 |R_jj| < wp |R_11| are dropped; <= 0 disables (default)  */
   double reorth_tol;         /* TSSVD_ORTHO_AUTO threshold (default 1e-13)               */
   int32_t max_jacobi_sweeps; /* cap on one-sided Jacobi sweeps in the small SVD (30)     */
-  int32_t reserved;
+  int32_t flags;             /* TSSVD_FLAG_* bits (default 0)                            */
   uint64_t seed;             /* Philox4x32-10 key used when lowrank_svd gets Omega==NULL */
 } tssvd_opts;
+
+/* Mixed mode: run the final sketch and B products on float32 matrix cores instead of the
+ * default exact three-way bfloat16 split of the float32 inputs (same float32-input result,
+ * float32 accumulation either way). */
+#define TSSVD_FLAG_F32_MFMA_FINAL 1
 
 /* Device-side record written (when non-NULL) at the end of every call. */
 typedef struct {
@@ -183,8 +189,8 @@ enum {
   TSSVD_PROF_LEAF_APPLY = 3,   /* TSQR leaf application (writes the tall factor)          */
   TSSVD_PROF_AX_BF16 = 4,      /* Y = A X, bfloat16 inputs (mixed power steps)            */
   TSSVD_PROF_ATQ_BF16 = 5,     /* Z = A^T Q, bfloat16 inputs (mixed power steps)          */
-  TSSVD_PROF_AX_F32 = 6,       /* Y = A X, float32 inputs (mixed final sketch)            */
-  TSSVD_PROF_ATQ_F32 = 7,      /* Z = A^T Q, float32 inputs (mixed B = Q^T A)             */
+  TSSVD_PROF_AX_FINAL = 6,     /* Y = A X, float32-exact inputs (mixed final sketch)      */
+  TSSVD_PROF_ATQ_FINAL = 7,    /* Z = A^T Q, float32-exact inputs (mixed B = Q^T A)       */
   TSSVD_PROF_KINDS = 8
 };
 int tssvd_profile_enable(int on);      /* on != 0: start recording (counters reset)      */

@@ -52,8 +52,9 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def make_opts(prec=PREC_FP64, ortho=ORTHO_AUTO, working_precision=0.0, reorth_tol=1e-13,
-              max_jacobi_sweeps=30, seed=None) -> N.Opts:
+              max_jacobi_sweeps=30, seed=None, flags=0) -> N.Opts:
     o = N.default_opts()
+    o.flags = int(flags)
     o.prec, o.ortho = int(prec), int(ortho)
     o.working_precision = float(working_precision)
     o.reorth_tol = float(reorth_tol)

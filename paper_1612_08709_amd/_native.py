@@ -19,6 +19,7 @@ F64, F32 = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 ORTHO_AUTO, ORTHO_ONCE, ORTHO_TWICE = 0, 1, 2
 NUM_NONFINITE, NUM_NO_CONVERGENCE = 1, 2
+FLAG_F32_MFMA_FINAL = 1
 
 # every exported symbol declared in include/tssvd.h
 EXPORTS = (
@@ -31,15 +32,15 @@ EXPORTS = (
 )
 
 PROF_AX, PROF_ATQ, PROF_LEAF_FACTOR, PROF_LEAF_APPLY = 0, 1, 2, 3
-PROF_AX_BF16, PROF_ATQ_BF16, PROF_AX_F32, PROF_ATQ_F32 = 4, 5, 6, 7
+PROF_AX_BF16, PROF_ATQ_BF16, PROF_AX_FINAL, PROF_ATQ_FINAL = 4, 5, 6, 7
 PROF_NAMES = {0: "gemm_ax_f64", 1: "gemm_atq_f64", 2: "tsqr_leaf_factor", 3: "tsqr_leaf_apply",
-              4: "ax_bf16", 5: "atq_bf16", 6: "ax_f32", 7: "atq_f32"}
+              4: "ax_bf16", 5: "atq_bf16", 6: "ax_final", 7: "atq_final"}
 
 
 class Opts(C.Structure):
     _fields_ = [("prec", C.c_int32), ("ortho", C.c_int32), ("working_precision", C.c_double),
                 ("reorth_tol", C.c_double), ("max_jacobi_sweeps", C.c_int32),
-                ("reserved", C.c_int32), ("seed", C.c_uint64)]
+                ("flags", C.c_int32), ("seed", C.c_uint64)]
 
 
 class Info(C.Structure):

@@ -346,22 +346,23 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   // Products with A.  FP64: float64 MFMA on A as stored.  MIXED: bfloat16 inputs in the
   // power steps, float32 inputs for the last sketch and for B (the operand is packed first).
   const float* A32 = static_cast<const float*>(A);
+  const bool f32_final = (o.flags & TSSVD_FLAG_F32_MFMA_FINAL) != 0;
   auto ax = [&](const double* Xs, bool last) -> hipError_t {
     if (!mixed) return gemm_ax_f64(A, a_dtype, lda, m, n, Xs, li, li, w.Y, li, s, TSSVD_PROF_AX);
-    const int kind = last ? MIX_F32_AX : MIX_BF16;
+    const int kind = !last ? MIX_BF16 : (f32_final ? MIX_F32_AX : MIX_BF16X3);
     hipError_t e = pack_operand(Xs, n, li, li, kind, w.pack, s);
     if (e != hipSuccess) return e;
     return gemm_ax_mixed(A32, lda, m, n, w.pack, li, w.Y, li, kind, s,
-                         last ? TSSVD_PROF_AX_F32 : TSSVD_PROF_AX_BF16);
+                         last ? TSSVD_PROF_AX_FINAL : TSSVD_PROF_AX_BF16);
   };
   auto atq = [&](bool last) -> hipError_t {
     if (!mixed)
       return gemm_atq_f64(A, a_dtype, lda, m, n, w.Y, li, li, w.Z, li, w.part, s, TSSVD_PROF_ATQ);
-    const int kind = last ? MIX_F32_ROWS : MIX_BF16;
+    const int kind = !last ? MIX_BF16 : (f32_final ? MIX_F32_ROWS : MIX_BF16X3);
     hipError_t e = pack_operand(w.Y, m, li, li, kind, w.pack, s);
     if (e != hipSuccess) return e;
     return gemm_atq_mixed(A32, lda, m, n, w.pack, li, w.Z, li, w.part, kind, s,
-                          last ? TSSVD_PROF_ATQ_F32 : TSSVD_PROF_ATQ_BF16);
+                          last ? TSSVD_PROF_ATQ_FINAL : TSSVD_PROF_ATQ_BF16);
   };
   // Algorithm 5: subspace iteration
   TRY(ax(w.X, q == 0));                                                        // A Q~_0

@@ -82,16 +82,58 @@ __global__ void k_pack_f32_rows(const double* __restrict__ S, int64_t K, int l, 
   P[idx] = (r < K && c < l) ? (float)S[r * lds + c] : 0.0f;
 }
 
+// Exact three-way bfloat16 split of a float32 value: a = a1 + a2 + a3 (each a1, a2, a3 is
+// the nearest bfloat16 of what is left; a float32 significand has 24 bits = 3 x 8).
+__device__ __forceinline__ void split3(float a, __bf16& a1, __bf16& a2, __bf16& a3) {
+  a1 = (__bf16)a;
+  const float r1 = a - (float)a1;
+  a2 = (__bf16)r1;
+  a3 = (__bf16)(r1 - (float)a2);
+}
+
+// Three bfloat16 pieces of the float64 operand: P[piece * nfrag + frag] (piece 0..2).
+__global__ void k_pack_bf16x3(const double* __restrict__ S, int64_t K, int l, int lds, int NT,
+                              int64_t nkb, bf16x8* __restrict__ P) {
+  const int64_t nfrag = nkb * NT * 64;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nfrag) return;
+  const int lane = (int)(idx & 63);
+  const int64_t t = idx >> 6;
+  const int nt = (int)(t % NT);
+  const int64_t kb = t / NT;
+  const int col = 16 * nt + (lane & 15);
+  const int64_t k0 = 32 * kb + 8 * (lane >> 4);
+  bf16x8 v1, v2, v3;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t k = k0 + e;
+    const double x = (k < K && col < l) ? S[k * lds + col] : 0.0;
+    const __bf16 x1 = (__bf16)(float)x;
+    const double r1 = x - (double)(float)x1;
+    const __bf16 x2 = (__bf16)(float)r1;
+    const double r2 = r1 - (double)(float)x2;
+    v1[e] = x1;
+    v2[e] = x2;
+    v3[e] = (__bf16)(float)r2;
+  }
+  P[idx] = v1;
+  P[nfrag + idx] = v2;
+  P[2 * nfrag + idx] = v3;
+}
+
 __device__ __forceinline__ bool aligned16(const void* p) {
   return (reinterpret_cast<uintptr_t>(p) & 15) == 0;
 }
 
 // ---------------------------------------------------------------- Y = A X, bf16
-template <int RT, int NT>
+// PIECES = 1: bfloat16 inputs.  PIECES = 3: A and X split exactly into three bfloat16
+// pieces; the six products a1x1 + a1x2 + a2x1 + a2x2 + a1x3 + a3x1 (all terms down to
+// relative weight 2^-24) give float32-input accuracy at bfloat16 matrix-core rate.
+template <int RT, int NT, int PIECES>
 __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, int64_t lda,
                                                  int64_t m, int n,
-                                                 const bf16x8* __restrict__ Xp, int l,
-                                                 double* __restrict__ Y, int ldy) {
+                                                 const bf16x8* __restrict__ Xp, int64_t nfrag,
+                                                 int l, double* __restrict__ Y, int ldy) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int64_t rbase = (int64_t)blockIdx.x * (64 * RT) + (int64_t)wave * (16 * RT);
@@ -111,7 +153,7 @@ __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, in
   const int nkb = (n + 31) / 32;
   for (int kb = 0; kb < nkb; ++kb) {
     const int k0 = 32 * kb + 8 * g;
-    bf16x8 a[RT], b[NT];
+    bf16x8 a[PIECES][RT], b[PIECES][NT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       float v[8];
@@ -125,15 +167,37 @@ __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, in
 #pragma unroll
         for (int e = 0; e < 8; ++e) v[e] = (rok[rt] && k0 + e < n) ? p[e] : 0.0f;
       }
+      if (PIECES == 1) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) a[rt][e] = (__bf16)v[e];
+        for (int e = 0; e < 8; ++e) a[0][rt][e] = (__bf16)v[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          __bf16 x1, x2, x3;
+          split3(v[e], x1, x2, x3);
+          a[0][rt][e] = x1;
+          a[1 % PIECES][rt][e] = x2;
+          a[2 % PIECES][rt][e] = x3;
+        }
+      }
     }
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) b[nt] = Xp[((int64_t)kb * NT + nt) * 64 + lane];
+    for (int pc = 0; pc < PIECES; ++pc)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) b[pc][nt] = Xp[pc * nfrag + ((int64_t)kb * NT + nt) * 64 + lane];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mfma_bf16(a[rt], b[nt], acc[rt][nt]);
+      for (int nt = 0; nt < NT; ++nt) {
+        if (PIECES == 3) {
+          acc[rt][nt] = mfma_bf16(a[2 % PIECES][rt], b[0][nt], acc[rt][nt]);
+          acc[rt][nt] = mfma_bf16(a[0][rt], b[2 % PIECES][nt], acc[rt][nt]);
+          acc[rt][nt] = mfma_bf16(a[1 % PIECES][rt], b[1 % PIECES][nt], acc[rt][nt]);
+          acc[rt][nt] = mfma_bf16(a[1 % PIECES][rt], b[0][nt], acc[rt][nt]);
+          acc[rt][nt] = mfma_bf16(a[0][rt], b[1 % PIECES][nt], acc[rt][nt]);
+        }
+        acc[rt][nt] = mfma_bf16(a[0][rt], b[0][nt], acc[rt][nt]);
+      }
   }
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -223,11 +287,11 @@ __device__ __forceinline__ void mx_tile(int total, int ncol, int& chunk, int& ct
   ct = ok ? L - chunk * ncol : 0;
 }
 
-template <int NT>
+template <int NT, int PIECES>
 __global__ __launch_bounds__(256) void k_atq_bf16(const float* __restrict__ A, int64_t lda,
                                                   int64_t m, int n,
-                                                  const bf16x8* __restrict__ Qp, int l,
-                                                  int ncol, int nchunk, int64_t chunk_rows,
+                                                  const bf16x8* __restrict__ Qp, int64_t nfrag,
+                                                  int l, int ncol, int nchunk, int64_t chunk_rows,
                                                   double* __restrict__ part) {
   int chunk, ct;
   bool ok;
@@ -247,36 +311,52 @@ __global__ __launch_bounds__(256) void k_atq_bf16(const float* __restrict__ A, i
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[e][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int64_t rb = r0; rb < r1; rb += 32) {
-    bf16x8 a[4];
+    bf16x8 a[PIECES][4];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int64_t row = rb + 8 * g + t;
       const float* p = A + row * lda + cb;
-      float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f;
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
       if (row < r1) {
         if (cvec && aligned16(p)) {
           const float4 x = *reinterpret_cast<const float4*>(p);
-          v0 = x.x; v1 = x.y; v2 = x.z; v3 = x.w;
+          v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
         } else {
-          v0 = (cb + 0 < n) ? p[0] : 0.f;
-          v1 = (cb + 1 < n) ? p[1] : 0.f;
-          v2 = (cb + 2 < n) ? p[2] : 0.f;
-          v3 = (cb + 3 < n) ? p[3] : 0.f;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = (cb + e < n) ? p[e] : 0.f;
         }
       }
-      a[0][t] = (__bf16)v0;
-      a[1][t] = (__bf16)v1;
-      a[2][t] = (__bf16)v2;
-      a[3][t] = (__bf16)v3;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (PIECES == 1) a[0][e][t] = (__bf16)v[e];
+        else {
+          __bf16 x1, x2, x3;
+          split3(v[e], x1, x2, x3);
+          a[0][e][t] = x1;
+          a[1 % PIECES][e][t] = x2;
+          a[2 % PIECES][e][t] = x3;
+        }
+      }
     }
     const int64_t kb = rb >> 5;
-    bf16x8 b[NT];
+    bf16x8 b[PIECES][NT];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) b[nt] = Qp[(kb * NT + nt) * 64 + lane];
+    for (int pc = 0; pc < PIECES; ++pc)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) b[pc][nt] = Qp[pc * nfrag + (kb * NT + nt) * 64 + lane];
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[e][nt] = mfma_bf16(a[e], b[nt], acc[e][nt]);
+      for (int nt = 0; nt < NT; ++nt) {
+        if (PIECES == 3) {
+          acc[e][nt] = mfma_bf16(a[2 % PIECES][e], b[0][nt], acc[e][nt]);
+          acc[e][nt] = mfma_bf16(a[0][e], b[2 % PIECES][nt], acc[e][nt]);
+          acc[e][nt] = mfma_bf16(a[1 % PIECES][e], b[1 % PIECES][nt], acc[e][nt]);
+          acc[e][nt] = mfma_bf16(a[1 % PIECES][e], b[0][nt], acc[e][nt]);
+          acc[e][nt] = mfma_bf16(a[0][e], b[1 % PIECES][nt], acc[e][nt]);
+        }
+        acc[e][nt] = mfma_bf16(a[0][e], b[0][nt], acc[e][nt]);
+      }
   }
   double* P = part + (int64_t)chunk * n * l;
 #pragma unroll
@@ -377,7 +457,7 @@ size_t mixed_partials(int64_t m, int64_t n, int l) {
 size_t mixed_pack_bytes(int64_t K, int l) {
   const int NT = (l + 15) / 16;
   const int64_t Kpad = (K + 31) / 32 * 32;
-  return (size_t)Kpad * 16 * NT * 4;  // the largest of the three packings (f32, padded)
+  return (size_t)Kpad * 16 * NT * 6;  // the largest packing: three bfloat16 pieces
 }
 
 hipError_t pack_operand(const double* S, int64_t K, int l, int lds, int kind, void* P,
@@ -388,6 +468,11 @@ hipError_t pack_operand(const double* S, int64_t K, int l, int lds, int kind, vo
     const int64_t tot = nkb * NT * 64;
     hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, S, K,
                        l, lds, NT, nkb, (bf16x8*)P);
+  } else if (kind == MIX_BF16X3) {
+    const int64_t nkb = (K + 31) / 32;
+    const int64_t tot = nkb * NT * 64;
+    hipLaunchKernelGGL(k_pack_bf16x3, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, S,
+                       K, l, lds, NT, nkb, (bf16x8*)P);
   } else if (kind == MIX_F32_AX) {
     const int64_t nkb = (K + 15) / 16;
     const int64_t tot = nkb * NT * 64;
@@ -407,9 +492,13 @@ static void launch_ax_mixed(const float* A, int64_t lda, int64_t m, int64_t n, c
                             int l, double* Y, int ldy, int kind, hipStream_t s) {
   constexpr int RT = 2;
   const unsigned grid = (unsigned)((m + 64 * RT - 1) / (64 * RT));
+  const int64_t nfrag = (int64_t)((n + 31) / 32) * NT * 64;
   if (kind == MIX_BF16)
-    hipLaunchKernelGGL((k_ax_bf16<RT, NT>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
-                       (const bf16x8*)Xp, l, Y, ldy);
+    hipLaunchKernelGGL((k_ax_bf16<RT, NT, 1>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
+                       (const bf16x8*)Xp, nfrag, l, Y, ldy);
+  else if (kind == MIX_BF16X3)
+    hipLaunchKernelGGL((k_ax_bf16<RT, NT, 3>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
+                       (const bf16x8*)Xp, nfrag, l, Y, ldy);
   else
     hipLaunchKernelGGL((k_ax_f32<RT, NT>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
                        (const float*)Xp, l, Y, ldy);
@@ -440,9 +529,13 @@ static void launch_atq_mixed(const float* A, int64_t lda, int64_t m, int64_t n, 
   mx_grid(m, n, ncol, nchunk, cr);
   const int total = ncol * nchunk;
   const int grid = ((total + 7) / 8) * 8;
+  const int64_t nfrag = ((m + 31) / 32) * NT * 64;
   if (kind == MIX_BF16)
-    hipLaunchKernelGGL((k_atq_bf16<NT>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
-                       (const bf16x8*)Qp, l, ncol, nchunk, cr, part);
+    hipLaunchKernelGGL((k_atq_bf16<NT, 1>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
+                       (const bf16x8*)Qp, nfrag, l, ncol, nchunk, cr, part);
+  else if (kind == MIX_BF16X3)
+    hipLaunchKernelGGL((k_atq_bf16<NT, 3>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
+                       (const bf16x8*)Qp, nfrag, l, ncol, nchunk, cr, part);
   else
     hipLaunchKernelGGL((k_atq_f32<NT>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
                        (const float*)Qp, l, ncol, nchunk, cr, part);

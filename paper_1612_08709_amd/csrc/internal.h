@@ -86,6 +86,7 @@ hipError_t reduce_chunks(const double* part, int nchunk, int64_t n, int l, doubl
 constexpr int MIX_BF16 = 0;    // bfloat16 inputs, float32 accumulation
 constexpr int MIX_F32_AX = 1;  // float32 inputs, packed for Y = A X
 constexpr int MIX_F32_ROWS = 2;  // float32 inputs, padded rows for Z = A^T Q
+constexpr int MIX_BF16X3 = 3;  // float32-accurate inputs as three exact bfloat16 pieces
 size_t mixed_partials(int64_t m, int64_t n, int l);
 size_t mixed_pack_bytes(int64_t K, int l);
 // Pack the K x l float64 operand S (stride lds) for the kernels below.

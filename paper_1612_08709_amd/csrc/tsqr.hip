@@ -371,7 +371,7 @@ void tsqr_carve(TsqrPlan& p, Carver& c) {
     p.Slev[l] = c.take<double>((size_t)p.cnt[l] * n * n);
   }
   for (int l = 0; l + 1 < L; ++l) {
-    p.Vtree[l] = c.take<double>((size_t)p.cnt[l + 1] * n * p.B);
+    p.Vtree[l] = c.take<double>((size_t)p.cnt[l + 1] * n * 16 * p.nc);
     p.tautree[l] = c.take<double>((size_t)p.cnt[l + 1] * n);
   }
 }
@@ -393,8 +393,10 @@ static hipError_t factor_impl(const TsqrPlan& p, const void* A, int a_dtype, int
                        (const float*)A, lda, p.m, n, p.bpw, p.nblocks, p.Vleaf, p.tauleaf,
                        p.Rlev[0], p.gate);
   if (prof) prof_end(TSSVD_PROF_LEAF_FACTOR, s);
+  // merge nodes hold only n <= 16*NC nonzero block rows: use blocks of 16*NC rows there
+  const size_t lds_t = (size_t)(tri_size(n) + 2 * 16 * NC + n) * sizeof(double);
   for (size_t l = 0; l + 1 < p.cnt.size(); ++l)
-    hipLaunchKernelGGL((k_tree_factor<NC, NR>), dim3(p.cnt[l + 1]), dim3(256), lds, s,
+    hipLaunchKernelGGL((k_tree_factor<NC, NC>), dim3(p.cnt[l + 1]), dim3(256), lds_t, s,
                        p.Rlev[l], p.cnt[l], n, p.Rlev[l + 1], p.Vtree[l], p.tautree[l], p.gate);
   return hipGetLastError();
 }
@@ -409,7 +411,7 @@ static hipError_t apply_impl(const TsqrPlan& p, const double* S, int k, double* 
   if (e != hipSuccess) return e;
   const size_t lds = (size_t)n * k * sizeof(double);
   for (int l = L - 2; l >= 0; --l)
-    hipLaunchKernelGGL((k_tree_apply<NC, NR>), dim3(p.cnt[l + 1]), dim3(256), lds, s,
+    hipLaunchKernelGGL((k_tree_apply<NC, NC>), dim3(p.cnt[l + 1]), dim3(256), lds, s,
                        p.Slev[l + 1], p.cnt[l], n, k, p.Vtree[l], p.tautree[l], p.Slev[l],
                        p.gate);
   if (prof) prof_begin(TSSVD_PROF_LEAF_APPLY, s);

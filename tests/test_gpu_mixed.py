@@ -77,3 +77,18 @@ def test_mixed_deterministic_bitwise():
     r2 = [host(x) for x in T.lowrank_svd(Ad, 20, 30, 2, Om, prec=T.PREC_MIXED)[:3]]
     for a, b in zip(r1, r2):
         assert np.array_equal(a, b)
+
+
+def test_f32_mfma_final_flag_same_result_class():
+    """The float32-MFMA final products (flag) and the default exact bf16 split agree."""
+    A32, _ = _workload4_like(12000, 900, 77, r=300)
+    Om = dev(sm.sketch(900, 40, 77))
+    Ad = dev(A32)
+    a = T.lowrank_svd(Ad, 30, 40, 2, Om, prec=T.PREC_MIXED)
+    b = T.lowrank_svd(Ad, 30, 40, 2, Om, prec=T.PREC_MIXED, flags=1)
+    torch.cuda.synchronize()
+    A64 = A32.astype(np.float64)
+    ea = checks.spectral_residual(A64, host(a[0]), host(a[1]), host(a[2]), tol=1e-9)
+    eb = checks.spectral_residual(A64, host(b[0]), host(b[1]), host(b[2]), tol=1e-9)
+    assert abs(ea - eb) <= 1e-6 * host(a[1])[0]
+    assert sigma_rel(host(a[1]), host(b[1])) < 1e-5
