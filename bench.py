@@ -201,12 +201,40 @@ def leg_tssvd(workload, steps, warmup, dtype_name=None):
     return out
 
 
+def leg_backward(steps, warmup):
+    """Forward + hand-written backward on the differentiation workload (100,000 x 1,000 f32)."""
+    import torch
+    import paper_1612_08709_amd as T
+    from synth import matrices as sm, torch_gen
+    spec, A = generate(5)
+    m, n, k, l, q = spec["m"], spec["n"], spec["k"], spec["l"], spec["q"]
+    Om = torch_gen.sketch(n, l, 5, "cuda:0")
+    gU = torch.from_numpy(sm.gaussian((m, k), 5, "GU")).to("cuda:0")
+    gS = torch.from_numpy(sm.gaussian(k, 5, "w")).to("cuda:0")
+    gV = torch.from_numpy(sm.gaussian((n, k), 5, "GV")).to("cuda:0")
+    call = T.LowrankCall(A, k, l, q)
+    U, S, V = call.run(Om)
+    fwd, _ = time_calls(lambda: call.run(Om), steps, warmup)
+    bwd, prof = time_calls(lambda: T.lowrank_svd_backward(A, k, l, q, Om, U, S, V, gU, gS, gV),
+                           steps, warmup)
+    abytes = m * n * A.element_size()
+    passes_bwd = 2 * q + 2 + 2 * q + 1  # recomputed forward + reverse passes
+    out = dict(workload="forward + backward, 100000 x 1000 f32 (k=16, l=24, q=2)",
+               forward_ms=round(fwd * 1e3, 4), backward_ms=round(bwd * 1e3, 4),
+               backward_gbs_A=round(passes_bwd * abytes / bwd / 1e9, 2),
+               backward_kernels={kk: dict(total_ms=round(v[0], 4), launches=v[1])
+                                 for kk, v in prof.items()})
+    del A
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--legs", default="w1,w2,w3")
+    ap.add_argument("--legs", default="w1,w2,w3,w5")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=100_000)
     ap.add_argument("--calib-copy", action="store_true",
@@ -254,6 +282,8 @@ def main():
                                   kernels=r2["kernels"])
                 del A2
                 torch.cuda.empty_cache()
+            elif leg == "w5":
+                legs["w5"] = leg_backward(args.steps, args.warmup)
             elif leg == "w3":
                 legs["w3_f64"] = leg_tssvd(3, args.steps, args.warmup, "f64")
                 legs["w3_f32"] = leg_tssvd(3, args.steps, args.warmup, "f32")

@@ -158,10 +158,14 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
 
 /* ---------------------------------------------------------------------------------------
  * lowrank_svd_backward — dL/dA for a scalar loss L(U, S, V) of lowrank_svd's outputs,
- * given the cotangents gU = dL/dU (m x k), gS = dL/dS (k), gV = dL/dV (n x k); any of the
- * three may be NULL (zero).  The derivative is that of the implemented forward map with
- * Omega held fixed: the forward is recomputed from (A, Omega) inside the call, so U, S, V
- * must be the outputs of lowrank_svd on the same A, Omega, k, l, q and options.
+ * given the cotangents gU = dL/dU (m x k, stride ldu), gS = dL/dS (k), gV = dL/dV
+ * (n x k, stride ldv); any of the three may be NULL (zero).  The derivative is that of the
+ * implemented forward map with Omega held fixed (Omega == NULL: the Philox sketch of
+ * opts->seed).  The forward is recomputed from (A, Omega) inside the call with one
+ * orthonormalization per factorization (a second pass on an orthonormal factor has
+ * identity derivative), so U, S, V must come from lowrank_svd on the same A, Omega, k,
+ * l, q and options; they are not read.  2q+2 passes over A recompute the forward, 2q+1
+ * passes and one m x (2q+2)l x n product form gA.
  *   gA : m x n, a_dtype, stride ldga (written)
  * Requires opts->prec == TSSVD_PREC_FP64 and working_precision <= 0.
  * ------------------------------------------------------------------------------------- */

@@ -398,6 +398,75 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
 }
 
 // ---------------------------------------------------------------- lowrank_svd_backward
+}  // extern "C"
+
+namespace {
+
+struct BackwardWs {
+  TsqrPlan pY, pZ;
+  int K2;
+  double *Lcat, *Rcat, *Rj, *Rtj, *Y, *Z, *Xbar, *Qtbar, *I, *Ub, *sig, *Ws, *Wfull, *G1, *G2,
+      *A1, *KB, *Kw, *Kv, *UbkT, *M, *Rinv, *K1, *K2m, *part;
+  size_t bytes;
+};
+
+BackwardWs backward_layout(int64_t m, int64_t n, int k, int l, int q, void* work) {
+  BackwardWs w;
+  Carver c(work);
+  w.pY = tsqr_plan(m, l);
+  tsqr_carve(w.pY, c);
+  w.pZ = tsqr_plan(n, l);
+  tsqr_carve(w.pZ, c);
+  w.K2 = (2 * q + 2) * l;
+  const size_t ll = (size_t)l * l;
+  w.Lcat = c.take<double>((size_t)m * w.K2);
+  w.Rcat = c.take<double>((size_t)n * w.K2);
+  w.Rj = c.take<double>((size_t)(q + 1) * ll);
+  w.Rtj = c.take<double>((size_t)(q + 1) * ll);
+  w.Y = c.take<double>((size_t)m * l);
+  w.Z = c.take<double>((size_t)n * l);
+  w.Xbar = c.take<double>((size_t)m * l);
+  w.Qtbar = c.take<double>((size_t)n * l);
+  w.I = c.take<double>(ll);
+  w.Ub = c.take<double>(ll);
+  w.sig = c.take<double>(l);
+  w.Ws = c.take<double>(ll);
+  w.Wfull = c.take<double>((size_t)n * l);
+  w.G1 = c.take<double>((size_t)l * k);
+  w.G2 = c.take<double>((size_t)l * k);
+  w.A1 = c.take<double>(ll);
+  w.KB = c.take<double>(ll);
+  w.Kw = c.take<double>(ll);
+  w.Kv = c.take<double>((size_t)k * l);
+  w.UbkT = c.take<double>((size_t)k * l);
+  w.M = c.take<double>(ll);
+  w.Rinv = c.take<double>(ll);
+  w.K1 = c.take<double>(ll);
+  w.K2m = c.take<double>(ll);
+  size_t np = atq_partials(m, n, l);
+  const size_t cand[3] = {atq_partials(m, l, l), atq_partials(n, l, l), atq_partials(m, l, k)};
+  for (size_t x : cand)
+    if (x > np) np = x;
+  w.part = c.take<double>(np);
+  w.bytes = c.off + 256;
+  return w;
+}
+
+// Ybar = [Xbar - Qx copyltu(Xbar^T Qx)] R^-T, written to out (rows x l, stride ldo).
+hipError_t qr_back(BackwardWs& w, const double* Xbar, int64_t ldx, const double* Qx, int64_t ldq,
+                   const double* R, int64_t rows, int l, double* out, int64_t ldo,
+                   hipStream_t s) {
+  hipError_t e = gemm_atq_f64(Xbar, TSSVD_F64, ldx, rows, l, Qx, (int)ldq, l, w.M, l, w.part, s);
+  if (e != hipSuccess) return e;
+  e = bw_qr_coef(w.M, R, l, w.Rinv, w.K1, w.K2m, s);
+  if (e != hipSuccess) return e;
+  return rmul(Xbar, ldx, l, w.K1, Qx, ldq, l, w.K2m, rows, l, out, ldo, false, s);
+}
+
+}  // namespace
+
+extern "C" {
+
 int lowrank_svd_backward_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t l, int64_t q,
                                          int32_t a_dtype, const tssvd_opts* opts,
                                          size_t* bytes) {
@@ -405,7 +474,8 @@ int lowrank_svd_backward_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_
   int st = lowrank_check((const void*)1, a_dtype, m, n, n, k, l, q);
   if (st != TSSVD_OK) return st;
   (void)opts;
-  return TSSVD_E_UNSUPPORTED;
+  *bytes = backward_layout(m, n, (int)k, (int)l, (int)q, nullptr).bytes;
+  return TSSVD_OK;
 }
 
 int lowrank_svd_backward(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
@@ -416,9 +486,79 @@ int lowrank_svd_backward(const void* A, int32_t a_dtype, int64_t m, int64_t n, i
                          const tssvd_opts* opts, void* stream) {
   int st = lowrank_check(A, a_dtype, m, n, lda, k, l, q);
   if (st != TSSVD_OK) return st;
-  (void)Omega; (void)U; (void)ldu; (void)S; (void)V; (void)ldv; (void)gU; (void)gS; (void)gV;
-  (void)gA; (void)ldga; (void)info; (void)work; (void)work_bytes; (void)opts; (void)stream;
-  return TSSVD_E_UNSUPPORTED;
+  if (!gA || ldga < n || ldu < k || ldv < k) return TSSVD_E_INVALID_ARG;
+  const tssvd_opts o = resolve(opts);
+  if (check_opts(o) != TSSVD_OK) return TSSVD_E_INVALID_ARG;
+  if (o.prec != TSSVD_PREC_FP64 || o.working_precision > 0.0) return TSSVD_E_UNSUPPORTED;
+  (void)U; (void)S; (void)V;  // the forward is recomputed from (A, Omega); see the header
+  const int ki = (int)k, li = (int)l, qi = (int)q;
+  BackwardWs w = backward_layout(m, n, ki, li, qi, work);
+  if (!work || work_bytes < w.bytes) return TSSVD_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const int K2 = w.K2;
+  const size_t ll = (size_t)li * li;
+  auto Lblk = [&](int b) { return w.Lcat + (size_t)b * li; };
+  auto Rblk = [&](int b) { return w.Rcat + (size_t)b * li; };
+
+  TRY(info_init(info, s));
+  TRY(fill_identity(w.I, li, li, s));
+  // ---- recompute the forward (Algorithm 7, one orthonormalization per factorization)
+  if (Omega)
+    TRY(copy_matrix(Omega, n, li, l, Rblk(1), K2, s));
+  else {
+    TRY(philox_sketch(w.Z, n, li, o.seed, s));
+    TRY(copy_matrix(w.Z, n, li, l, Rblk(1), K2, s));
+  }
+  for (int j = 1; j <= qi; ++j) {
+    TRY(gemm_ax_f64(A, a_dtype, lda, m, n, Rblk(j), K2, li, w.Y, li, s));
+    TRY(tsqr_factor(w.pY, w.Y, TSSVD_F64, l, s));
+    TRY(copy_matrix(tsqr_root(w.pY), l, li, l, w.Rj + (j - 1) * ll, l, s));
+    TRY(tsqr_apply(w.pY, w.I, li, Lblk(qi + 1 + j), K2, s));               // Q_j
+    TRY(gemm_atq_f64(A, a_dtype, lda, m, n, Lblk(qi + 1 + j), K2, li, w.Z, li, w.part, s));
+    TRY(tsqr_factor(w.pZ, w.Z, TSSVD_F64, l, s));
+    TRY(copy_matrix(tsqr_root(w.pZ), l, li, l, w.Rtj + (j - 1) * ll, l, s));
+    TRY(tsqr_apply(w.pZ, w.I, li, Rblk(1 + j), K2, s));                    // Q~_j
+  }
+  TRY(gemm_ax_f64(A, a_dtype, lda, m, n, Rblk(1 + qi), K2, li, w.Y, li, s));
+  TRY(tsqr_factor(w.pY, w.Y, TSSVD_F64, l, s));
+  TRY(copy_matrix(tsqr_root(w.pY), l, li, l, w.Rj + qi * ll, l, s));
+  TRY(tsqr_apply(w.pY, w.I, li, Lblk(0), K2, s));                          // Q
+  TRY(gemm_atq_f64(A, a_dtype, lda, m, n, Lblk(0), K2, li, w.Z, li, w.part, s));  // B^T
+  TRY(tsqr_factor(w.pZ, w.Z, TSSVD_F64, l, s));
+  TRY(jacobi_svd(tsqr_root(w.pZ), li, li, 1, 0.0, o.max_jacobi_sweeps, 0, w.Ub, w.sig, w.Ws,
+                 info, s));
+  TRY(tsqr_apply(w.pZ, w.Ws, li, w.Wfull, l, s));                          // W = Q_B W~
+  TRY(sign_fix_cols(w.Wfull, n, li, ki, w.Ub, li, li, s));                 // as in the forward
+
+  // ---- SVD layer: G1 = Q^T gU, G2 = W^T gV, core coefficients, Bbar^T
+  if (gU)
+    TRY(gemm_atq_f64(Lblk(0), TSSVD_F64, K2, m, l, gU, (int)ldu, ki, w.G1, ki, w.part, s));
+  else
+    TRY(zero_fill(w.G1, (int64_t)li * ki, s));
+  if (gV)
+    TRY(gemm_atq_f64(w.Wfull, TSSVD_F64, l, n, l, gV, (int)ldv, ki, w.G2, ki, w.part, s));
+  else
+    TRY(zero_fill(w.G2, (int64_t)li * ki, s));
+  TRY(bw_svd_core(w.Ub, w.sig, w.G1, w.G2, gS, li, ki, w.A1, w.KB, w.Kw, w.Kv, w.UbkT, s));
+  TRY(rmul(w.Wfull, l, li, w.Kw, gV, ldv, gV ? ki : 0, w.Kv, n, li, Rblk(0), K2, false, s));
+  // ---- Qbar = A Bbar^T + gU Ub_k^T, then the QR layer of the last factorization
+  TRY(gemm_ax_f64(A, a_dtype, lda, m, n, Rblk(0), K2, li, w.Xbar, li, s, TSSVD_PROF_AX));
+  if (gU) TRY(rmul(gU, ldu, ki, w.UbkT, nullptr, 0, 0, nullptr, m, li, w.Xbar, l, true, s));
+  TRY(qr_back(w, w.Xbar, l, Lblk(0), K2, w.Rj + qi * ll, m, li, Lblk(qi + 1), K2, s));
+  // ---- walk the subspace iteration backwards
+  for (int j = qi; j >= 1; --j) {
+    TRY(gemm_atq_f64(A, a_dtype, lda, m, n, Lblk(j + 1), K2, li, w.Qtbar, li, w.part, s,
+                     TSSVD_PROF_ATQ));                                      // A^T Ybar_{j+1}
+    TRY(qr_back(w, w.Qtbar, l, Rblk(1 + j), K2, w.Rtj + (j - 1) * ll, n, li, Rblk(qi + 1 + j),
+                K2, s));                                                    // Zbar_j
+    TRY(gemm_ax_f64(A, a_dtype, lda, m, n, Rblk(qi + 1 + j), K2, li, w.Xbar, li, s,
+                    TSSVD_PROF_AX));                                        // A Zbar_j
+    TRY(qr_back(w, w.Xbar, l, Lblk(qi + 1 + j), K2, w.Rj + (j - 1) * ll, m, li, Lblk(j), K2,
+                s));                                                        // Ybar_j
+  }
+  // ---- Abar = [Q | Ybar_1..Ybar_{q+1} | Q_1..Q_q] [Bbar^T | Q~_0..Q~_q | Zbar_1..Zbar_q]^T
+  TRY(gemm_nt(w.Lcat, K2, w.Rcat, K2, m, n, K2, gA, a_dtype, ldga, s));
+  return hip_status(hipGetLastError());
 }
 
 // ---------------------------------------------------------------- measurement support

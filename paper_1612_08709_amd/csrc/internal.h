@@ -101,6 +101,19 @@ hipError_t gemm_atq_mixed(const float* A, int64_t lda, int64_t m, int64_t n, con
                           int l, double* Z, int ldz, double* part, int kind, hipStream_t s,
                           int prof = -1);
 
+// ------------------------------------------------------------------ reverse pass
+hipError_t bw_svd_core(const double* Ub, const double* sig, const double* G1, const double* G2,
+                       const double* Sbar, int l, int k, double* A1, double* KB, double* Kw,
+                       double* Kv, double* UbkT, hipStream_t s);
+hipError_t bw_qr_coef(const double* M, const double* R, int l, double* Rinv, double* K1,
+                      double* K2, hipStream_t s);
+hipError_t rmul(const double* X1, int64_t ld1, int k1, const double* K1, const double* X2,
+                int64_t ld2, int k2, const double* K2, int64_t rows, int kout, double* out,
+                int64_t ldo, bool accum, hipStream_t s);
+hipError_t zero_fill(double* p, int64_t count, hipStream_t s);
+hipError_t gemm_nt(const double* L, int64_t ldl, const double* R, int64_t ldr, int64_t m,
+                   int64_t n, int K, void* C, int c_dtype, int64_t ldc, hipStream_t s);
+
 // ------------------------------------------------------------------ misc
 hipError_t fill_identity(double* S, int n, int k, hipStream_t s);
 hipError_t philox_sketch(double* X, int64_t n, int l, uint64_t seed, hipStream_t s);
