@@ -82,6 +82,9 @@ def kernel_model(name, m, n, l, a_bytes_per_elem):
     return None
 
 
+SIMPLE_DATA = False  # counter runs: plain Gaussian entries (traffic does not depend on values)
+
+
 def generate(workload, dtype_name=None):
     import torch
     from synth import matrices as sm, torch_gen
@@ -89,6 +92,8 @@ def generate(workload, dtype_name=None):
     dn = dtype_name or spec["dtype"]
     dt = torch.float64 if dn == "f64" else torch.float32
     log(f"[bench] generating workload {workload}: {spec['m']} x {spec['n']} {dn}")
+    if SIMPLE_DATA:
+        return spec, torch_gen.gaussian((spec["m"], spec["n"]), workload, "A", "cuda:0", dtype=dt)
     A = torch_gen.planted(spec["m"], spec["n"], spec["sigma"], workload, "cuda:0",
                           noise=spec.get("noise", 0.0), dtype=dt, rank=spec.get("rank"))
     return spec, A
@@ -240,10 +245,14 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB read + 1 GiB write elementwise kernel first (counter "
                          "calibration for the HBM traffic figures)")
+    ap.add_argument("--simple-data", action="store_true",
+                    help="Gaussian matrices instead of planted spectra (hardware-counter runs)")
     args = ap.parse_args()
+    global SIMPLE_DATA
+    SIMPLE_DATA = args.simple_data
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(this build has no multi-GPU path).", file=sys.stderr)
+              "(the library runs on a single GPU).", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

@@ -29,7 +29,33 @@ __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
 // ---------------------------------------------------------------- Y = A X
 // 256 threads; wave w owns rows base + 16*(RT*w + rt) + (0..15); all NT column tiles.
 // Per step of 16 along k, lane (i = lane%16, g = lane/16) loads A[row][k0+4g .. k0+4g+3]
-// and uses element s in the s-th MFMA: k-slot g of MFMA s is column k0 + 4g + s.
+// (one 16- or 32-byte vector when aligned) and uses element s in the s-th MFMA: k-slot g
+// of MFMA s is column k0 + 4g + s.  The next step's A is loaded before this step's MFMAs.
+__device__ __forceinline__ bool al16(const void* p) {
+  return (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+}
+
+__device__ __forceinline__ void load4(const double* p, bool full, int valid, double (&v)[4]) {
+  if (full && al16(p)) {
+    const double2 x0 = *reinterpret_cast<const double2*>(p);
+    const double2 x1 = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = x0.x; v[1] = x0.y; v[2] = x1.x; v[3] = x1.y;
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = (s < valid) ? p[s] : 0.0;
+  }
+}
+
+__device__ __forceinline__ void load4(const float* p, bool full, int valid, double (&v)[4]) {
+  if (full && al16(p)) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = (s < valid) ? (double)p[s] : 0.0;
+  }
+}
+
 template <int RT, int NT, typename TA>
 __global__ __launch_bounds__(256) void k_gemm_ax_f64(const TA* __restrict__ A, int64_t lda,
                                                      int64_t m, int n,
@@ -51,15 +77,30 @@ __global__ __launch_bounds__(256) void k_gemm_ax_f64(const TA* __restrict__ A, i
     rok[rt] = row < m;
     arow[rt] = A + (rok[rt] ? row : 0) * lda;
   }
+  auto load_a = [&](int k0, double (&a)[RT][4]) {
+    const int kb = k0 + 4 * g;
+    const int valid = n - kb;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      if (rok[rt] && valid > 0) {
+        load4(arow[rt] + kb, valid >= 4, valid, a[rt]);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[rt][s] = 0.0;
+      }
+    }
+  };
+  double a[RT][4];
+  load_a(0, a);
   for (int k0 = 0; k0 < n; k0 += 16) {
-    double a[RT][4], x[NT][4];
+    double an[RT][4], x[NT][4];
+    const int kn = (k0 + 16 < n) ? k0 + 16 : k0;
+    load_a(kn, an);
     const int kb = k0 + 4 * g;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int kk = kb + s;
       const bool kok = kk < n;
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) a[rt][s] = (kok && rok[rt]) ? ld_elem(arow[rt] + kk) : 0.0;
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         const int col = 16 * nt + li;
@@ -72,6 +113,10 @@ __global__ __launch_bounds__(256) void k_gemm_ax_f64(const TA* __restrict__ A, i
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mfma_f64(a[rt][s], x[nt][s], acc[rt][nt]);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[rt][s] = an[rt][s];
   }
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -154,23 +199,36 @@ __global__ __launch_bounds__(256) void k_gemm_atq_f64(const TA* __restrict__ A, 
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f64x4{0.0, 0.0, 0.0, 0.0};
   const int cb = cw + 4 * li;
-  for (int64_t rq = r0; rq < r1; rq += 4) {
+  const int cvalid = n - cb;
+  auto load = [&](int64_t rq, double (&a)[4], double (&q)[NT]) {
     const int64_t row = rq + g;
     const bool rok = row < r1;
     const int64_t rr = rok ? row : r0;
-    double a[4], q[NT];
-    const TA* ap = A + rr * lda + cb;
+    if (rok && cvalid > 0) {
+      load4(A + rr * lda + cb, cvalid >= 4, cvalid, a);
+    } else {
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) a[mt] = (rok && cb + mt < n) ? ld_elem(ap + mt) : 0.0;
+      for (int mt = 0; mt < 4; ++mt) a[mt] = 0.0;
+    }
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int col = 16 * nt + li;
       q[nt] = (rok && col < l) ? Q[rr * ldq + col] : 0.0;
     }
+  };
+  double a[4], q[NT];
+  load(r0, a, q);
+  for (int64_t rq = r0; rq < r1; rq += 4) {
+    double an[4], qn[NT];
+    load((rq + 4 < r1) ? rq + 4 : rq, an, qn);
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_f64(a[mt], q[nt], acc[mt][nt]);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) a[mt] = an[mt];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) q[nt] = qn[nt];
   }
   double* P = part + (int64_t)chunk * n * l;
 #pragma unroll

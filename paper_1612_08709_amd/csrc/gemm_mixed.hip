@@ -33,7 +33,8 @@ __device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c) {
 }
 
 // ---------------------------------------------------------------- operand packing
-// bf16 B-operand fragments of a K x l float64 matrix S (stride lds):
+// bf16 B-operand fragments of a K x l float64 matrix S (stride lds), each entry rounded
+// once from its float64 value to the nearest bfloat16 (ties to even):
 //   P[(kb*NT + nt)*64 + lane][e] = S[32 kb + 8 (lane/16) + e][16 nt + lane%16]  (0 outside)
 __global__ void k_pack_bf16(const double* __restrict__ S, int64_t K, int l, int lds, int NT,
                             int64_t nkb, bf16x8* __restrict__ P) {
@@ -49,7 +50,7 @@ __global__ void k_pack_bf16(const double* __restrict__ S, int64_t K, int l, int 
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int64_t k = k0 + e;
-    v[e] = (__bf16)((k < K && col < l) ? (float)S[k * lds + col] : 0.0f);
+    v[e] = (__bf16)((k < K && col < l) ? S[k * lds + col] : 0.0);
   }
   P[idx] = v;
 }
@@ -91,7 +92,8 @@ __device__ __forceinline__ void split3(float a, __bf16& a1, __bf16& a2, __bf16& 
   a3 = (__bf16)(r1 - (float)a2);
 }
 
-// Three bfloat16 pieces of the float64 operand: P[piece * nfrag + frag] (piece 0..2).
+// Three bfloat16 pieces of the float64 operand, each the nearest bfloat16 of what is left
+// (x = x1 + x2 + x3 + O(2^-24 |x|)): P[piece * nfrag + frag] (piece 0..2).
 __global__ void k_pack_bf16x3(const double* __restrict__ S, int64_t K, int l, int lds, int NT,
                               int64_t nkb, bf16x8* __restrict__ P) {
   const int64_t nfrag = nkb * NT * 64;
@@ -108,13 +110,13 @@ __global__ void k_pack_bf16x3(const double* __restrict__ S, int64_t K, int l, in
   for (int e = 0; e < 8; ++e) {
     const int64_t k = k0 + e;
     const double x = (k < K && col < l) ? S[k * lds + col] : 0.0;
-    const __bf16 x1 = (__bf16)(float)x;
-    const double r1 = x - (double)(float)x1;
-    const __bf16 x2 = (__bf16)(float)r1;
-    const double r2 = r1 - (double)(float)x2;
+    const __bf16 x1 = (__bf16)x;
+    const double r1 = x - (double)x1;
+    const __bf16 x2 = (__bf16)r1;
+    const double r2 = r1 - (double)x2;
     v1[e] = x1;
     v2[e] = x2;
-    v3[e] = (__bf16)(float)r2;
+    v3[e] = (__bf16)r2;
   }
   P[idx] = v1;
   P[nfrag + idx] = v2;
@@ -129,6 +131,26 @@ __device__ __forceinline__ bool aligned16(const void* p) {
 // PIECES = 1: bfloat16 inputs.  PIECES = 3: A and X split exactly into three bfloat16
 // pieces; the six products a1x1 + a1x2 + a2x1 + a2x2 + a1x3 + a3x1 (all terms down to
 // relative weight 2^-24) give float32-input accuracy at bfloat16 matrix-core rate.
+// The A values of step kb+1 are loaded before the products of step kb (software
+// pipelining), so each wave keeps two steps of A in flight.
+template <int RT>
+__device__ __forceinline__ void ax_load(const float* const (&arow)[RT], const bool (&rok)[RT],
+                                        int k0, int n, float (&v)[RT][8]) {
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const float* p = arow[rt] + k0;
+    if (rok[rt] && k0 + 8 <= n && aligned16(p)) {
+      const float4 x0 = *reinterpret_cast<const float4*>(p);
+      const float4 x1 = *reinterpret_cast<const float4*>(p + 4);
+      v[rt][0] = x0.x; v[rt][1] = x0.y; v[rt][2] = x0.z; v[rt][3] = x0.w;
+      v[rt][4] = x1.x; v[rt][5] = x1.y; v[rt][6] = x1.z; v[rt][7] = x1.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[rt][e] = (rok[rt] && k0 + e < n) ? p[e] : 0.0f;
+    }
+  }
+}
+
 template <int RT, int NT, int PIECES>
 __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, int64_t lda,
                                                  int64_t m, int n,
@@ -151,40 +173,33 @@ __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, in
     arow[rt] = A + (rok[rt] ? row : 0) * lda;
   }
   const int nkb = (n + 31) / 32;
+  float va[RT][8];
+  ax_load<RT>(arow, rok, 8 * g, n, va);
   for (int kb = 0; kb < nkb; ++kb) {
-    const int k0 = 32 * kb + 8 * g;
+    float vn[RT][8];
+    const int kbn = (kb + 1 < nkb) ? kb + 1 : kb;
+    ax_load<RT>(arow, rok, 32 * kbn + 8 * g, n, vn);
     bf16x8 a[PIECES][RT], b[PIECES][NT];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      float v[8];
-      const float* p = arow[rt] + k0;
-      if (rok[rt] && k0 + 8 <= n && aligned16(p)) {
-        const float4 x0 = *reinterpret_cast<const float4*>(p);
-        const float4 x1 = *reinterpret_cast<const float4*>(p + 4);
-        v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
-        v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
-      } else {
+    for (int pc = 0; pc < PIECES; ++pc)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = (rok[rt] && k0 + e < n) ? p[e] : 0.0f;
-      }
+      for (int nt = 0; nt < NT; ++nt) b[pc][nt] = Xp[pc * nfrag + ((int64_t)kb * NT + nt) * 64 + lane];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
       if (PIECES == 1) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) a[0][rt][e] = (__bf16)v[e];
+        for (int e = 0; e < 8; ++e) a[0][rt][e] = (__bf16)va[rt][e];
       } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           __bf16 x1, x2, x3;
-          split3(v[e], x1, x2, x3);
+          split3(va[rt][e], x1, x2, x3);
           a[0][rt][e] = x1;
           a[1 % PIECES][rt][e] = x2;
           a[2 % PIECES][rt][e] = x3;
         }
       }
     }
-#pragma unroll
-    for (int pc = 0; pc < PIECES; ++pc)
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) b[pc][nt] = Xp[pc * nfrag + ((int64_t)kb * NT + nt) * 64 + lane];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -198,6 +213,10 @@ __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, in
         }
         acc[rt][nt] = mfma_bf16(a[0][rt], b[0][nt], acc[rt][nt]);
       }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) va[rt][e] = vn[rt][e];
   }
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -278,6 +297,9 @@ __global__ __launch_bounds__(256) void k_ax_f32(const float* __restrict__ A, int
 // ---------------------------------------------------------------- Z = A^T Q, bf16 / f32
 // Workgroup = (row chunk, 256-column tile), wave w owns 64 columns cw = c0 + 64 w.
 constexpr int MX_COLS = 256;
+#ifndef AX_RT
+#define AX_RT 4
+#endif
 
 __device__ __forceinline__ void mx_tile(int total, int ncol, int& chunk, int& ct, bool& ok) {
   const int per = (total + 7) / 8;
@@ -285,6 +307,28 @@ __device__ __forceinline__ void mx_tile(int total, int ncol, int& chunk, int& ct
   ok = L < total;
   chunk = ok ? L / ncol : 0;
   ct = ok ? L - chunk * ncol : 0;
+}
+
+__device__ __forceinline__ void atq_load(const float* __restrict__ A, int64_t lda, int64_t rb,
+                                         int g, int64_t r1, int cb, int n, bool cvec,
+                                         float (&v)[8][4]) {
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int64_t row = rb + 8 * g + t;
+    const float* p = A + row * lda + cb;
+    if (row < r1) {
+      if (cvec && aligned16(p)) {
+        const float4 x = *reinterpret_cast<const float4*>(p);
+        v[t][0] = x.x; v[t][1] = x.y; v[t][2] = x.z; v[t][3] = x.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[t][e] = (cb + e < n) ? p[e] : 0.f;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[t][e] = 0.f;
+    }
+  }
 }
 
 template <int NT, int PIECES>
@@ -310,40 +354,32 @@ __global__ __launch_bounds__(256) void k_atq_bf16(const float* __restrict__ A, i
   for (int e = 0; e < 4; ++e)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[e][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float va[8][4];
+  atq_load(A, lda, r0, g, r1, cb, n, cvec, va);
   for (int64_t rb = r0; rb < r1; rb += 32) {
-    bf16x8 a[PIECES][4];
+    float vn[8][4];
+    const int64_t rbn = (rb + 32 < r1) ? rb + 32 : rb;
+    atq_load(A, lda, rbn, g, r1, cb, n, cvec, vn);
+    const int64_t kb = rb >> 5;
+    bf16x8 a[PIECES][4], b[PIECES][NT];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int64_t row = rb + 8 * g + t;
-      const float* p = A + row * lda + cb;
-      float v[4] = {0.f, 0.f, 0.f, 0.f};
-      if (row < r1) {
-        if (cvec && aligned16(p)) {
-          const float4 x = *reinterpret_cast<const float4*>(p);
-          v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-        } else {
+    for (int pc = 0; pc < PIECES; ++pc)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = (cb + e < n) ? p[e] : 0.f;
-        }
-      }
+      for (int nt = 0; nt < NT; ++nt) b[pc][nt] = Qp[pc * nfrag + (kb * NT + nt) * 64 + lane];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        if (PIECES == 1) a[0][e][t] = (__bf16)v[e];
-        else {
+        if (PIECES == 1) {
+          a[0][e][t] = (__bf16)va[t][e];
+        } else {
           __bf16 x1, x2, x3;
-          split3(v[e], x1, x2, x3);
+          split3(va[t][e], x1, x2, x3);
           a[0][e][t] = x1;
           a[1 % PIECES][e][t] = x2;
           a[2 % PIECES][e][t] = x3;
         }
       }
-    }
-    const int64_t kb = rb >> 5;
-    bf16x8 b[PIECES][NT];
-#pragma unroll
-    for (int pc = 0; pc < PIECES; ++pc)
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) b[pc][nt] = Qp[pc * nfrag + (kb * NT + nt) * 64 + lane];
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -357,6 +393,10 @@ __global__ __launch_bounds__(256) void k_atq_bf16(const float* __restrict__ A, i
         }
         acc[e][nt] = mfma_bf16(a[0][e], b[0][nt], acc[e][nt]);
       }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) va[t][e] = vn[t][e];
   }
   double* P = part + (int64_t)chunk * n * l;
 #pragma unroll
@@ -490,18 +530,19 @@ hipError_t pack_operand(const double* S, int64_t K, int l, int lds, int kind, vo
 template <int NT>
 static void launch_ax_mixed(const float* A, int64_t lda, int64_t m, int64_t n, const void* Xp,
                             int l, double* Y, int ldy, int kind, hipStream_t s) {
-  constexpr int RT = 2;
+  constexpr int RT = AX_RT;
   const unsigned grid = (unsigned)((m + 64 * RT - 1) / (64 * RT));
   const int64_t nfrag = (int64_t)((n + 31) / 32) * NT * 64;
-  if (kind == MIX_BF16)
+  if (kind == MIX_F32_AX) {
+    constexpr int RT2 = 2;
+    hipLaunchKernelGGL((k_ax_f32<RT2, NT>), dim3((unsigned)((m + 64 * RT2 - 1) / (64 * RT2))),
+                       dim3(256), 0, s, A, lda, m, (int)n, (const float*)Xp, l, Y, ldy);
+  } else if (kind == MIX_BF16)
     hipLaunchKernelGGL((k_ax_bf16<RT, NT, 1>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
                        (const bf16x8*)Xp, nfrag, l, Y, ldy);
-  else if (kind == MIX_BF16X3)
+  else
     hipLaunchKernelGGL((k_ax_bf16<RT, NT, 3>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
                        (const bf16x8*)Xp, nfrag, l, Y, ldy);
-  else
-    hipLaunchKernelGGL((k_ax_f32<RT, NT>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
-                       (const float*)Xp, l, Y, ldy);
 }
 
 hipError_t gemm_ax_mixed(const float* A, int64_t lda, int64_t m, int64_t n, const void* Xp,

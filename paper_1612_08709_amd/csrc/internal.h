@@ -33,7 +33,8 @@ struct TsqrPlan {
   int64_t nblocks = 0;
   int W = 0;             // leaf workgroups
   int bpw = 0;           // blocks per leaf workgroup
-  std::vector<int> cnt;  // cnt[0] = W, cnt[L+1] = ceil(cnt[L]/2), last = 1
+  int G = 0;             // child factors stacked per merge block (fan-in G + 1)
+  std::vector<int> cnt;  // cnt[0] = W, cnt[L+1] = ceil(cnt[L]/(G+1)), last = 1
   // workspace regions (filled by carve)
   double* Vleaf = nullptr;  // nblocks * n * B   reflector tails, column-major per block
   double* tauleaf = nullptr;  // nblocks * n

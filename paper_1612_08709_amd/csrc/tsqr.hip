@@ -6,10 +6,11 @@
 // factors the stacked matrix [R; A_t].  Reflector j acts on row j of R and on the block
 // rows only (R is upper triangular), so it is stored as its block part v_j plus tau_j:
 //   H_j = I - tau_j [e_j; v_j][e_j; v_j]^T,   H_{n-1} ... H_0 [R; A_t] = [R'; 0].
-// The per-workgroup factors are merged pairwise with the same step (carry = left R,
-// block = right R).  Q [S; 0] is formed top-down: every merge node maps its seed S to the
-// seeds of its two children, and every leaf workgroup maps its seed to its rows of Q by
-// walking its blocks backwards.
+// The per-workgroup factors are merged by a tree with the same step: a node's carry is its
+// first child's R and its block stacks the next G children's R factors (G = B / n), so
+// the tree has fan-in G + 1 and few levels.  Q [S; 0] is formed top-down: every merge node
+// maps its seed S to the seeds of its children, and every leaf workgroup maps its seed to
+// its rows of Q by walking its blocks backwards.
 //
 // Register layout (256 threads): thread (rg, cg), rg = lane & 15 ("row group", one
 // 16-lane DPP row), cg = (lane >> 4) + 4 * wave (column group, 0..15).  A block of
@@ -189,11 +190,14 @@ __global__ __launch_bounds__(256) void k_leaf_factor(const TA* __restrict__ A, i
   }
 }
 
-// One merge node per workgroup: [R_left; R_right] -> R.  A node without a right partner
-// copies R_left and records tau = 0 (identity) for the apply pass.
+// One merge node per workgroup.  Node i takes the fan = G + 1 factors first = i*fan ...:
+// the first is the carry R (LDS), the next G are stacked at row offsets 0, n, 2n, ... of
+// one block of B = 16*NR rows (G = B / n), so one structured factorization merges them
+// all: [R_0; R_1; ...; R_G] -> R.  Missing children are zero rows; a node with no child
+// beyond the first copies R_0 and records tau = 0 (identity) for the apply pass.
 template <int NC, int NR>
 __global__ __launch_bounds__(256) void k_tree_factor(const double* __restrict__ Rin, int nin,
-                                                     int n, double* __restrict__ Rout,
+                                                     int n, int G, double* __restrict__ Rout,
                                                      double* __restrict__ Vt,
                                                      double* __restrict__ taut,
                                                      const int* __restrict__ gate) {
@@ -205,27 +209,30 @@ __global__ __launch_bounds__(256) void k_tree_factor(const double* __restrict__ 
   double* vbuf = Rs + ts;
   double* tl = vbuf + 2 * B;
   const int tid = threadIdx.x, rg = ts_rg(), cg = ts_cg();
-  const int node = blockIdx.x, left = 2 * node, right = 2 * node + 1;
-  const double* RL = Rin + (int64_t)left * n * n;
+  const int node = blockIdx.x;
+  const int64_t first = (int64_t)node * (G + 1);
+  const double* R0 = Rin + first * n * n;
   double* Ro = Rout + (int64_t)node * n * n;
-  if (right >= nin) {
-    for (int i = tid; i < n * n; i += 256) Ro[i] = RL[i];
+  if (first + 1 >= nin) {
+    for (int i = tid; i < n * n; i += 256) Ro[i] = R0[i];
     for (int j = tid; j < n; j += 256) taut[(int64_t)node * n + j] = 0.0;
     return;
   }
   for (int i = tid; i < n * n; i += 256) {
     const int r = i / n, c = i - r * n;
-    if (c >= r) Rs[tri_idx(r, c, n)] = RL[i];
+    if (c >= r) Rs[tri_idx(r, c, n)] = R0[i];
   }
-  const double* RR = Rin + (int64_t)right * n * n;
   double a[NR][NC];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int row = rg + 16 * r;
+    const int ch = row / n, lr = row - ch * n;  // child 1 + ch, its row lr
+    const bool live = ch < G && first + 1 + ch < nin;
+    const double* Rc = Rin + (first + 1 + ch) * n * n + (int64_t)lr * n;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int col = cg + 16 * c;
-      a[r][c] = (row < n && col < n) ? RR[row * n + col] : 0.0;
+      a[r][c] = (live && col < n) ? Rc[col] : 0.0;
     }
   }
   __syncthreads();
@@ -247,10 +254,12 @@ __global__ __launch_bounds__(256) void k_tree_factor(const double* __restrict__ 
   }
 }
 
-// Seeds of one tree level from the level above: node seed S -> (S_left, S_right).
+// Seeds of one tree level from the level above: node seed S (n x k) -> the seeds of its
+// children, [S_0; S_1; ...; S_G] = H_0 ... H_{n-1} [S; 0] with S_i at block rows
+// (i-1)*n ... i*n-1 for i >= 1.
 template <int NC, int NR>
 __global__ __launch_bounds__(256) void k_tree_apply(const double* __restrict__ Sin,
-                                                    int nchild, int n, int k,
+                                                    int nchild, int n, int k, int G,
                                                     const double* __restrict__ Vt,
                                                     const double* __restrict__ taut,
                                                     double* __restrict__ Sout,
@@ -260,7 +269,9 @@ __global__ __launch_bounds__(256) void k_tree_apply(const double* __restrict__ S
   constexpr int B = 16 * NR;
   double* Ss = smem;
   const int tid = threadIdx.x, rg = ts_rg(), cg = ts_cg();
-  const int node = blockIdx.x, left = 2 * node, right = 2 * node + 1;
+  const int node = blockIdx.x;
+  const int64_t first = (int64_t)node * (G + 1);
+  const bool merged = first + 1 < nchild;
   const double* S = Sin + (int64_t)node * n * k;
   for (int i = tid; i < n * k; i += 256) Ss[i] = S[i];
   __syncthreads();
@@ -269,21 +280,24 @@ __global__ __launch_bounds__(256) void k_tree_apply(const double* __restrict__ S
   for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int c = 0; c < NC; ++c) y[r][c] = 0.0;
-  if (right < nchild)
+  if (merged)
     apply_block_reverse<NC, NR>(y, Ss, Vt + (int64_t)node * n * B, taut + (int64_t)node * n,
                                 n, k);
   __syncthreads();
-  double* SL = Sout + (int64_t)left * n * k;
-  for (int i = tid; i < n * k; i += 256) SL[i] = Ss[i];
-  if (right < nchild) {
-    double* SR = Sout + (int64_t)right * n * k;
+  double* S0 = Sout + first * n * k;
+  for (int i = tid; i < n * k; i += 256) S0[i] = Ss[i];
+  if (merged) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int row = rg + 16 * r;
+      const int ch = row / n, lr = row - ch * n;
+      if (ch < G && first + 1 + ch < nchild) {
+        double* Sc = Sout + (first + 1 + ch) * n * k + (int64_t)lr * k;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const int col = cg + 16 * c;
-        if (row < n && col < k) SR[row * k + col] = y[r][c];
+        for (int c = 0; c < NC; ++c) {
+          const int col = cg + 16 * c;
+          if (col < k) Sc[col] = y[r][c];
+        }
       }
     }
   }
@@ -345,15 +359,18 @@ TsqrPlan tsqr_plan(int64_t m, int n) {
   pick_tile(n, p.nc, p.nr);
   p.B = 16 * p.nr;
   p.nblocks = (m + p.B - 1) / p.B;
-  // Enough leaf workgroups to fill 256 CUs several times over, but blocks of work large
-  // enough that the merge tree stays a small fraction of the leaf work.
-  const int64_t target = 2048;
+  // About as many leaf workgroups as can be resident at once (two per CU for the wide
+  // tiles, four for the narrow ones): fewer would idle CUs, more would only deepen the
+  // merge tree.
+  const int64_t target = (p.nc >= 4) ? 512 : 1024;
   int64_t W = p.nblocks < target ? p.nblocks : target;
   p.bpw = (int)((p.nblocks + W - 1) / W);
   p.W = (int)((p.nblocks + p.bpw - 1) / p.bpw);
+  // merge nodes stack G = B / n child factors in one block: fan-in G + 1
+  p.G = p.B / n;
   p.cnt.clear();
   p.cnt.push_back(p.W);
-  while (p.cnt.back() > 1) p.cnt.push_back((p.cnt.back() + 1) / 2);
+  while (p.cnt.back() > 1) p.cnt.push_back((p.cnt.back() + p.G) / (p.G + 1));
   return p;
 }
 
@@ -371,7 +388,7 @@ void tsqr_carve(TsqrPlan& p, Carver& c) {
     p.Slev[l] = c.take<double>((size_t)p.cnt[l] * n * n);
   }
   for (int l = 0; l + 1 < L; ++l) {
-    p.Vtree[l] = c.take<double>((size_t)p.cnt[l + 1] * n * 16 * p.nc);
+    p.Vtree[l] = c.take<double>((size_t)p.cnt[l + 1] * n * p.B);
     p.tautree[l] = c.take<double>((size_t)p.cnt[l + 1] * n);
   }
 }
@@ -393,11 +410,10 @@ static hipError_t factor_impl(const TsqrPlan& p, const void* A, int a_dtype, int
                        (const float*)A, lda, p.m, n, p.bpw, p.nblocks, p.Vleaf, p.tauleaf,
                        p.Rlev[0], p.gate);
   if (prof) prof_end(TSSVD_PROF_LEAF_FACTOR, s);
-  // merge nodes hold only n <= 16*NC nonzero block rows: use blocks of 16*NC rows there
-  const size_t lds_t = (size_t)(tri_size(n) + 2 * 16 * NC + n) * sizeof(double);
   for (size_t l = 0; l + 1 < p.cnt.size(); ++l)
-    hipLaunchKernelGGL((k_tree_factor<NC, NC>), dim3(p.cnt[l + 1]), dim3(256), lds_t, s,
-                       p.Rlev[l], p.cnt[l], n, p.Rlev[l + 1], p.Vtree[l], p.tautree[l], p.gate);
+    hipLaunchKernelGGL((k_tree_factor<NC, NR>), dim3(p.cnt[l + 1]), dim3(256), lds, s,
+                       p.Rlev[l], p.cnt[l], n, p.G, p.Rlev[l + 1], p.Vtree[l], p.tautree[l],
+                       p.gate);
   return hipGetLastError();
 }
 
@@ -411,9 +427,9 @@ static hipError_t apply_impl(const TsqrPlan& p, const double* S, int k, double* 
   if (e != hipSuccess) return e;
   const size_t lds = (size_t)n * k * sizeof(double);
   for (int l = L - 2; l >= 0; --l)
-    hipLaunchKernelGGL((k_tree_apply<NC, NC>), dim3(p.cnt[l + 1]), dim3(256), lds, s,
-                       p.Slev[l + 1], p.cnt[l], n, k, p.Vtree[l], p.tautree[l], p.Slev[l],
-                       p.gate);
+    hipLaunchKernelGGL((k_tree_apply<NC, NR>), dim3(p.cnt[l + 1]), dim3(256), lds, s,
+                       p.Slev[l + 1], p.cnt[l], n, k, p.G, p.Vtree[l], p.tautree[l],
+                       p.Slev[l], p.gate);
   if (prof) prof_begin(TSSVD_PROF_LEAF_APPLY, s);
   hipLaunchKernelGGL((k_leaf_apply<NC, NR>), dim3(p.W), dim3(256), lds, s, p.Vleaf,
                      p.tauleaf, p.Slev[0], n, k, p.bpw, p.nblocks, p.m, out, ldo, p.gate);
