@@ -131,31 +131,57 @@ __device__ __forceinline__ bool aligned16(const void* p) {
 // PIECES = 1: bfloat16 inputs.  PIECES = 3: A and X split exactly into three bfloat16
 // pieces; the six products a1x1 + a1x2 + a2x1 + a2x2 + a1x3 + a3x1 (all terms down to
 // relative weight 2^-24) give float32-input accuracy at bfloat16 matrix-core rate.
-// The A values of step kb+1 are loaded before the products of step kb (software
-// pipelining), so each wave keeps two steps of A in flight.
-template <int RT>
-__device__ __forceinline__ void ax_load(const float* const (&arow)[RT], const bool (&rok)[RT],
-                                        int k0, int n, float (&v)[RT][8]) {
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    const float* p = arow[rt] + k0;
-    if (rok[rt] && k0 + 8 <= n && aligned16(p)) {
-      const float4 x0 = *reinterpret_cast<const float4*>(p);
-      const float4 x1 = *reinterpret_cast<const float4*>(p + 4);
-      v[rt][0] = x0.x; v[rt][1] = x0.y; v[rt][2] = x0.z; v[rt][3] = x0.w;
-      v[rt][4] = x1.x; v[rt][5] = x1.y; v[rt][6] = x1.z; v[rt][7] = x1.w;
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[rt][e] = (rok[rt] && k0 + e < n) ? p[e] : 0.0f;
-    }
+//
+// Wave w owns rows base + 16*(RT*w + rt) + (0..15).  Per step of 32 along k, lane
+// (i = lane%16, g = lane/16) reads A[row][32kb + 8g .. 32kb + 8g + 7] (two 16-byte loads
+// when VEC: A 16-byte aligned and lda a multiple of 4).  The main loop runs over the full
+// steps with no bounds tests (rows past m read row m-1 and are not stored); a ragged last
+// step reads with tests.  The A (and, for one piece, X) fragments of step kb+1 are loaded
+// before the products of step kb.
+template <int PIECES>
+__device__ __forceinline__ void to_pieces(float x, __bf16 (&p)[3]) {
+  if (PIECES == 1) {
+    p[0] = (__bf16)x;
+  } else {
+    split3(x, p[0], p[1], p[2]);
   }
 }
 
 template <int RT, int NT, int PIECES>
+__device__ __forceinline__ void ax_products(const float (&v)[RT][8],
+                                            const bf16x8 (&b)[PIECES][NT],
+                                            f32x4 (&acc)[RT][NT]) {
+  bf16x8 a[PIECES][RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __bf16 p[3];
+      to_pieces<PIECES>(v[rt][e], p);
+#pragma unroll
+      for (int pc = 0; pc < PIECES; ++pc) a[pc][rt][e] = p[pc];
+    }
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      if (PIECES == 3) {
+        acc[rt][nt] = mfma_bf16(a[2 % PIECES][rt], b[0][nt], acc[rt][nt]);
+        acc[rt][nt] = mfma_bf16(a[0][rt], b[2 % PIECES][nt], acc[rt][nt]);
+        acc[rt][nt] = mfma_bf16(a[1 % PIECES][rt], b[1 % PIECES][nt], acc[rt][nt]);
+        acc[rt][nt] = mfma_bf16(a[1 % PIECES][rt], b[0][nt], acc[rt][nt]);
+        acc[rt][nt] = mfma_bf16(a[0][rt], b[1 % PIECES][nt], acc[rt][nt]);
+      }
+      acc[rt][nt] = mfma_bf16(a[0][rt], b[0][nt], acc[rt][nt]);
+    }
+}
+
+template <int RT, int NT, int PIECES, bool VEC>
 __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, int64_t lda,
                                                  int64_t m, int n,
                                                  const bf16x8* __restrict__ Xp, int64_t nfrag,
                                                  int l, double* __restrict__ Y, int ldy) {
+  constexpr bool PREB = (PIECES == 1);  // prefetch X fragments too (registers allow it)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int64_t rbase = (int64_t)blockIdx.x * (64 * RT) + (int64_t)wave * (16 * RT);
@@ -165,58 +191,80 @@ __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, in
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
   const float* arow[RT];
-  bool rok[RT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
     const int64_t row = rbase + 16 * rt + li;
-    rok[rt] = row < m;
-    arow[rt] = A + (rok[rt] ? row : 0) * lda;
+    arow[rt] = A + (row < m ? row : m - 1) * lda + 8 * g;
   }
-  const int nkb = (n + 31) / 32;
-  float va[RT][8];
-  ax_load<RT>(arow, rok, 8 * g, n, va);
-  for (int kb = 0; kb < nkb; ++kb) {
-    float vn[RT][8];
-    const int kbn = (kb + 1 < nkb) ? kb + 1 : kb;
-    ax_load<RT>(arow, rok, 32 * kbn + 8 * g, n, vn);
-    bf16x8 a[PIECES][RT], b[PIECES][NT];
+  const bf16x8* xp = Xp + lane;
+  auto load_a = [&](int kb, float (&v)[RT][8]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const float* p = arow[rt] + 32 * kb;
+      if (VEC) {
+        const float4 x0 = *reinterpret_cast<const float4*>(p);
+        const float4 x1 = *reinterpret_cast<const float4*>(p + 4);
+        v[rt][0] = x0.x; v[rt][1] = x0.y; v[rt][2] = x0.z; v[rt][3] = x0.w;
+        v[rt][4] = x1.x; v[rt][5] = x1.y; v[rt][6] = x1.z; v[rt][7] = x1.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[rt][e] = p[e];
+      }
+    }
+  };
+  auto load_b = [&](int kb, bf16x8 (&b)[PIECES][NT]) {
 #pragma unroll
     for (int pc = 0; pc < PIECES; ++pc)
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) b[pc][nt] = Xp[pc * nfrag + ((int64_t)kb * NT + nt) * 64 + lane];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      if (PIECES == 1) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) a[0][rt][e] = (__bf16)va[rt][e];
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          __bf16 x1, x2, x3;
-          split3(va[rt][e], x1, x2, x3);
-          a[0][rt][e] = x1;
-          a[1 % PIECES][rt][e] = x2;
-          a[2 % PIECES][rt][e] = x3;
-        }
-      }
+      for (int nt = 0; nt < NT; ++nt) b[pc][nt] = xp[pc * nfrag + ((int64_t)kb * NT + nt) * 64];
+  };
+  // Two register sets, two steps in flight: the products of step kb run while the loads of
+  // step kb+1 are outstanding, and the loads of step kb+2 are issued only after them
+  // (scheduling barriers keep the compiler from hoisting loads above the products, which
+  // would make the wait for one step also wait for the next).  Steps past the last are
+  // clamped to it (a harmless reload).
+  const int nfull = n >> 5;
+  if (nfull > 0) {
+    float v0[RT][8], v1[RT][8];
+    bf16x8 b0[PIECES][NT], b1[PIECES][NT];
+    const int last = nfull - 1;
+    load_a(0, v0);
+    if (PREB) load_b(0, b0);
+    load_a(last < 1 ? last : 1, v1);
+    if (PREB) load_b(last < 1 ? last : 1, b1);
+    int kb = 0;
+    for (; kb + 2 <= nfull; kb += 2) {
+      if (!PREB) load_b(kb, b0);
+      ax_products<RT, NT, PIECES>(v0, b0, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      const int k2 = (kb + 2 < last) ? kb + 2 : last;
+      load_a(k2, v0);
+      if (PREB) load_b(k2, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (!PREB) load_b(kb + 1, b1);
+      ax_products<RT, NT, PIECES>(v1, b1, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      const int k3 = (kb + 3 < last) ? kb + 3 : last;
+      load_a(k3, v1);
+      if (PREB) load_b(k3, b1);
+      __builtin_amdgcn_sched_barrier(0);
     }
+    if (kb < nfull) {
+      if (!PREB) load_b(kb, b0);
+      ax_products<RT, NT, PIECES>(v0, b0, acc);
+    }
+  }
+  if ((nfull << 5) < n) {
+    // ragged last step: columns past n read as 0 (the packed X rows there are 0 as well)
+    const int k0 = (nfull << 5) + 8 * g;
+    float v[RT][8];
+    bf16x8 b[PIECES][NT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        if (PIECES == 3) {
-          acc[rt][nt] = mfma_bf16(a[2 % PIECES][rt], b[0][nt], acc[rt][nt]);
-          acc[rt][nt] = mfma_bf16(a[0][rt], b[2 % PIECES][nt], acc[rt][nt]);
-          acc[rt][nt] = mfma_bf16(a[1 % PIECES][rt], b[1 % PIECES][nt], acc[rt][nt]);
-          acc[rt][nt] = mfma_bf16(a[1 % PIECES][rt], b[0][nt], acc[rt][nt]);
-          acc[rt][nt] = mfma_bf16(a[0][rt], b[1 % PIECES][nt], acc[rt][nt]);
-        }
-        acc[rt][nt] = mfma_bf16(a[0][rt], b[0][nt], acc[rt][nt]);
-      }
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) va[rt][e] = vn[rt][e];
+      for (int e = 0; e < 8; ++e) v[rt][e] = (k0 + e < n) ? arow[rt][32 * nfull + e] : 0.f;
+    load_b(nfull, b);
+    ax_products<RT, NT, PIECES>(v, b, acc);
   }
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -300,6 +348,9 @@ constexpr int MX_COLS = 256;
 #ifndef AX_RT
 #define AX_RT 4
 #endif
+#ifndef AX_RT3
+#define AX_RT3 4
+#endif
 
 __device__ __forceinline__ void mx_tile(int total, int ncol, int& chunk, int& ct, bool& ok) {
   const int per = (total + 7) / 8;
@@ -309,29 +360,117 @@ __device__ __forceinline__ void mx_tile(int total, int ncol, int& chunk, int& ct
   ct = ok ? L - chunk * ncol : 0;
 }
 
-__device__ __forceinline__ void atq_load(const float* __restrict__ A, int64_t lda, int64_t rb,
-                                         int g, int64_t r1, int cb, int n, bool cvec,
-                                         float (&v)[8][4]) {
+// Z = A^T Q with bfloat16 pieces.  Per step of 32 rows, lane (i, g) reads the four
+// columns cb = cw + 4i .. cb+3 of rows rb + 8g + t (t < 8); MFMA tile e takes column
+// cb + e, k-slot (g, t) row rb + 8g + t.  Full steps run without bounds tests when FC;
+// the ragged last rows of the matrix are tested.
+template <int NT, int PIECES>
+__device__ __forceinline__ void atq_products(const float (&v)[8][4],
+                                             const bf16x8 (&b)[PIECES][NT],
+                                             f32x4 (&acc)[4][NT]) {
+  bf16x8 a[PIECES][4];
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const int64_t row = rb + 8 * g + t;
-    const float* p = A + row * lda + cb;
-    if (row < r1) {
-      if (cvec && aligned16(p)) {
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      __bf16 p[3];
+      to_pieces<PIECES>(v[t][e], p);
+#pragma unroll
+      for (int pc = 0; pc < PIECES; ++pc) a[pc][e][t] = p[pc];
+    }
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      if (PIECES == 3) {
+        acc[e][nt] = mfma_bf16(a[2 % PIECES][e], b[0][nt], acc[e][nt]);
+        acc[e][nt] = mfma_bf16(a[0][e], b[2 % PIECES][nt], acc[e][nt]);
+        acc[e][nt] = mfma_bf16(a[1 % PIECES][e], b[1 % PIECES][nt], acc[e][nt]);
+        acc[e][nt] = mfma_bf16(a[1 % PIECES][e], b[0][nt], acc[e][nt]);
+        acc[e][nt] = mfma_bf16(a[0][e], b[1 % PIECES][nt], acc[e][nt]);
+      }
+      acc[e][nt] = mfma_bf16(a[0][e], b[0][nt], acc[e][nt]);
+    }
+}
+
+template <int NT, int PIECES, bool FC>
+__device__ __forceinline__ void atq_rows(const float* __restrict__ A, int64_t lda, int n,
+                                         int cb, int g, int64_t r0, int64_t r1,
+                                         const bf16x8* __restrict__ qp, int64_t nfrag,
+                                         f32x4 (&acc)[4][NT]) {
+  constexpr bool PREB = (PIECES == 1);
+  auto load_a = [&](int64_t rb, float (&v)[8][4]) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const float* p = A + (rb + 8 * g + t) * lda + cb;
+      if (FC) {
         const float4 x = *reinterpret_cast<const float4*>(p);
         v[t][0] = x.x; v[t][1] = x.y; v[t][2] = x.z; v[t][3] = x.w;
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) v[t][e] = (cb + e < n) ? p[e] : 0.f;
       }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) v[t][e] = 0.f;
     }
+  };
+  auto load_b = [&](int64_t rb, bf16x8 (&b)[PIECES][NT]) {
+    const int64_t kb = rb >> 5;
+#pragma unroll
+    for (int pc = 0; pc < PIECES; ++pc)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) b[pc][nt] = qp[pc * nfrag + (kb * NT + nt) * 64];
+  };
+  const int64_t rfull = r0 + (((r1 - r0) >> 5) << 5);
+  if (rfull > r0) {
+    // two register sets, two steps in flight (as in Y = A X)
+    float v0[8][4], v1[8][4];
+    bf16x8 b0[PIECES][NT], b1[PIECES][NT];
+    const int64_t last = rfull - 32;
+    load_a(r0, v0);
+    if (PREB) load_b(r0, b0);
+    const int64_t r1st = (r0 + 32 < last) ? r0 + 32 : last;
+    load_a(r1st, v1);
+    if (PREB) load_b(r1st, b1);
+    int64_t rb = r0;
+    for (; rb + 64 <= rfull; rb += 64) {
+      if (!PREB) load_b(rb, b0);
+      atq_products<NT, PIECES>(v0, b0, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      const int64_t r2 = (rb + 64 < last) ? rb + 64 : last;
+      load_a(r2, v0);
+      if (PREB) load_b(r2, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (!PREB) load_b(rb + 32, b1);
+      atq_products<NT, PIECES>(v1, b1, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      const int64_t r3 = (rb + 96 < last) ? rb + 96 : last;
+      load_a(r3, v1);
+      if (PREB) load_b(r3, b1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (rb < rfull) {
+      if (!PREB) load_b(rb, b0);
+      atq_products<NT, PIECES>(v0, b0, acc);
+    }
+  }
+  if (rfull < r1) {
+    // ragged last rows (only the chunk that ends at m): rows past r1 read as 0
+    float v[8][4];
+    bf16x8 b[PIECES][NT];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t row = rfull + 8 * g + t;
+      const float* p = A + row * lda + cb;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[t][e] = (row < r1 && cb + e < n) ? p[e] : 0.f;
+    }
+    load_b(rfull, b);
+    atq_products<NT, PIECES>(v, b, acc);
   }
 }
 
-template <int NT, int PIECES>
+// FC: every wave's 64 columns lie inside A and rows are 16-byte aligned (n a multiple of
+// 64, A 16-byte aligned, lda a multiple of 4); otherwise every load is tested.
+template <int NT, int PIECES, bool FC>
 __global__ __launch_bounds__(256) void k_atq_bf16(const float* __restrict__ A, int64_t lda,
                                                   int64_t m, int n,
                                                   const bf16x8* __restrict__ Qp, int64_t nfrag,
@@ -348,56 +487,12 @@ __global__ __launch_bounds__(256) void k_atq_bf16(const float* __restrict__ A, i
   const int64_t r0 = (int64_t)chunk * chunk_rows;  // chunk_rows is a multiple of 32
   const int64_t r1 = (r0 + chunk_rows < m) ? r0 + chunk_rows : m;
   const int cb = cw + 4 * li;
-  const bool cvec = (cb + 4 <= n);
   f32x4 acc[4][NT];
 #pragma unroll
   for (int e = 0; e < 4; ++e)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[e][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float va[8][4];
-  atq_load(A, lda, r0, g, r1, cb, n, cvec, va);
-  for (int64_t rb = r0; rb < r1; rb += 32) {
-    float vn[8][4];
-    const int64_t rbn = (rb + 32 < r1) ? rb + 32 : rb;
-    atq_load(A, lda, rbn, g, r1, cb, n, cvec, vn);
-    const int64_t kb = rb >> 5;
-    bf16x8 a[PIECES][4], b[PIECES][NT];
-#pragma unroll
-    for (int pc = 0; pc < PIECES; ++pc)
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) b[pc][nt] = Qp[pc * nfrag + (kb * NT + nt) * 64 + lane];
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (PIECES == 1) {
-          a[0][e][t] = (__bf16)va[t][e];
-        } else {
-          __bf16 x1, x2, x3;
-          split3(va[t][e], x1, x2, x3);
-          a[0][e][t] = x1;
-          a[1 % PIECES][e][t] = x2;
-          a[2 % PIECES][e][t] = x3;
-        }
-      }
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        if (PIECES == 3) {
-          acc[e][nt] = mfma_bf16(a[2 % PIECES][e], b[0][nt], acc[e][nt]);
-          acc[e][nt] = mfma_bf16(a[0][e], b[2 % PIECES][nt], acc[e][nt]);
-          acc[e][nt] = mfma_bf16(a[1 % PIECES][e], b[1 % PIECES][nt], acc[e][nt]);
-          acc[e][nt] = mfma_bf16(a[1 % PIECES][e], b[0][nt], acc[e][nt]);
-          acc[e][nt] = mfma_bf16(a[0][e], b[1 % PIECES][nt], acc[e][nt]);
-        }
-        acc[e][nt] = mfma_bf16(a[0][e], b[0][nt], acc[e][nt]);
-      }
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) va[t][e] = vn[t][e];
-  }
+  atq_rows<NT, PIECES, FC>(A, lda, n, cb, g, r0, r1, Qp + lane, nfrag, acc);
   double* P = part + (int64_t)chunk * n * l;
 #pragma unroll
   for (int e = 0; e < 4; ++e)
@@ -532,17 +627,29 @@ static void launch_ax_mixed(const float* A, int64_t lda, int64_t m, int64_t n, c
                             int l, double* Y, int ldy, int kind, hipStream_t s) {
   constexpr int RT = AX_RT;
   const unsigned grid = (unsigned)((m + 64 * RT - 1) / (64 * RT));
+  const bool vec = (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda & 3) == 0;
   const int64_t nfrag = (int64_t)((n + 31) / 32) * NT * 64;
   if (kind == MIX_F32_AX) {
     constexpr int RT2 = 2;
     hipLaunchKernelGGL((k_ax_f32<RT2, NT>), dim3((unsigned)((m + 64 * RT2 - 1) / (64 * RT2))),
                        dim3(256), 0, s, A, lda, m, (int)n, (const float*)Xp, l, Y, ldy);
-  } else if (kind == MIX_BF16)
-    hipLaunchKernelGGL((k_ax_bf16<RT, NT, 1>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
-                       (const bf16x8*)Xp, nfrag, l, Y, ldy);
-  else
-    hipLaunchKernelGGL((k_ax_bf16<RT, NT, 3>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
-                       (const bf16x8*)Xp, nfrag, l, Y, ldy);
+  } else if (kind == MIX_BF16) {
+    if (vec)
+      hipLaunchKernelGGL((k_ax_bf16<RT, NT, 1, true>), dim3(grid), dim3(256), 0, s, A, lda, m,
+                         (int)n, (const bf16x8*)Xp, nfrag, l, Y, ldy);
+    else
+      hipLaunchKernelGGL((k_ax_bf16<RT, NT, 1, false>), dim3(grid), dim3(256), 0, s, A, lda, m,
+                         (int)n, (const bf16x8*)Xp, nfrag, l, Y, ldy);
+  } else {
+    constexpr int RT3 = AX_RT3;
+    const unsigned grid3 = (unsigned)((m + 64 * RT3 - 1) / (64 * RT3));
+    if (vec)
+      hipLaunchKernelGGL((k_ax_bf16<RT3, NT, 3, true>), dim3(grid3), dim3(256), 0, s, A, lda, m,
+                         (int)n, (const bf16x8*)Xp, nfrag, l, Y, ldy);
+    else
+      hipLaunchKernelGGL((k_ax_bf16<RT3, NT, 3, false>), dim3(grid3), dim3(256), 0, s, A, lda,
+                         m, (int)n, (const bf16x8*)Xp, nfrag, l, Y, ldy);
+  }
 }
 
 hipError_t gemm_ax_mixed(const float* A, int64_t lda, int64_t m, int64_t n, const void* Xp,
@@ -571,15 +678,26 @@ static void launch_atq_mixed(const float* A, int64_t lda, int64_t m, int64_t n, 
   const int total = ncol * nchunk;
   const int grid = ((total + 7) / 8) * 8;
   const int64_t nfrag = ((m + 31) / 32) * NT * 64;
-  if (kind == MIX_BF16)
-    hipLaunchKernelGGL((k_atq_bf16<NT, 1>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
-                       (const bf16x8*)Qp, nfrag, l, ncol, nchunk, cr, part);
-  else if (kind == MIX_BF16X3)
-    hipLaunchKernelGGL((k_atq_bf16<NT, 3>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
-                       (const bf16x8*)Qp, nfrag, l, ncol, nchunk, cr, part);
-  else
+  const bool vec =
+      (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda & 3) == 0 && (n & 63) == 0;
+  if (kind == MIX_BF16) {
+    if (vec)
+      hipLaunchKernelGGL((k_atq_bf16<NT, 1, true>), dim3(grid), dim3(256), 0, s, A, lda, m,
+                         (int)n, (const bf16x8*)Qp, nfrag, l, ncol, nchunk, cr, part);
+    else
+      hipLaunchKernelGGL((k_atq_bf16<NT, 1, false>), dim3(grid), dim3(256), 0, s, A, lda, m,
+                         (int)n, (const bf16x8*)Qp, nfrag, l, ncol, nchunk, cr, part);
+  } else if (kind == MIX_BF16X3) {
+    if (vec)
+      hipLaunchKernelGGL((k_atq_bf16<NT, 3, true>), dim3(grid), dim3(256), 0, s, A, lda, m,
+                         (int)n, (const bf16x8*)Qp, nfrag, l, ncol, nchunk, cr, part);
+    else
+      hipLaunchKernelGGL((k_atq_bf16<NT, 3, false>), dim3(grid), dim3(256), 0, s, A, lda, m,
+                         (int)n, (const bf16x8*)Qp, nfrag, l, ncol, nchunk, cr, part);
+  } else {
     hipLaunchKernelGGL((k_atq_f32<NT>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
                        (const float*)Qp, l, ncol, nchunk, cr, part);
+  }
 }
 
 hipError_t gemm_atq_mixed(const float* A, int64_t lda, int64_t m, int64_t n, const void* Qp,
