@@ -125,20 +125,154 @@ def run_lowrank(A, spec, prec, steps, warmup, workload):
                 S=S.cpu().numpy())
 
 
+# ---------------------------------------------------------------- hardware-counter traffic
+# HBM bytes per dispatch come from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+# WRITE_SIZE), summarized by --summarize-pmc into a profile next to this file.  Each counter
+# is scaled by what it reads for a plain elementwise kernel of known traffic (--calib-copy:
+# 1 GiB read + 1 GiB written).  A figure is used only while the kernel's source files are
+# byte-identical to the ones the counters were taken with.
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "paper_1612_08709_amd", "csrc")
+TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "hbm_traffic_workload4.md")
+KERNEL_SYMBOLS = {  # profile marker name -> (regex on the kernel symbol, source files)
+    "ax_bf16": (r"k_ax_bf16<\d+, \d+, 1[,>]", ["gemm_mixed.hip"]),
+    "atq_bf16": (r"k_atq_bf16<\d+, 1[,>]", ["gemm_mixed.hip"]),
+    "ax_final": (r"k_ax_bf16<\d+, \d+, 3[,>]", ["gemm_mixed.hip"]),
+    "atq_final": (r"k_atq_bf16<\d+, 3[,>]", ["gemm_mixed.hip"]),
+    "gemm_ax_f64": (r"k_gemm_ax_f64<\d+, \d+, float>", ["gemm.hip"]),
+    "gemm_atq_f64": (r"k_gemm_atq_f64<\d+, float>", ["gemm.hip"]),
+}
+CALIB_BYTES = 1 << 30
+
+
+def source_digest(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in list(files) + ["common.h", "internal.h"]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _pmc_rows(d):
+    import csv
+    path = os.path.join(d, "run_counter_collection.csv")
+    if not os.path.exists(path):
+        import glob
+        cands = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        path = cands[0]
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_pmc(fetch_dir, write_dir, command):
+    """Markdown summary of FETCH_SIZE / WRITE_SIZE per dispatch, calibrated, with a JSON line."""
+    import re
+    import statistics
+    out = {"calibration": {}, "kernels": {}}
+    per = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _pmc_rows(d)
+        calib = [r for r in rows if "MulFunctor" in r["Kernel_Name"]
+                 and int(r["Grid_Size"]) == (1 << 26)]
+        kib = float(calib[0]["Counter_Value"])
+        factor = CALIB_BYTES / (kib * 1024.0)
+        out["calibration"][counter] = dict(kib_for_1GiB=kib, factor=round(factor, 5))
+        for name, (rx, _) in KERNEL_SYMBOLS.items():
+            vals = [float(r["Counter_Value"]) for r in rows if re.search(rx, r["Kernel_Name"])]
+            if vals:
+                per.setdefault(name, {})[counter] = (statistics.median(vals), len(vals), factor)
+    lines = ["# HBM traffic per dispatch: randomized SVD, 500,000 x 8,000 float32 (l = 60)", "",
+             "Command (two runs, one counter each, from the repository root):", "",
+             "```", command, "```", "",
+             "Calibration: the 1 GiB elementwise kernel of `--calib-copy` (1 GiB read, "
+             "1 GiB written):", ""]
+    for c, v in out["calibration"].items():
+        lines.append(f"* {c}: {v['kib_for_1GiB']:.1f} KiB per GiB moved -> scale x{v['factor']}")
+    lines += ["", "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | "
+                  "source digest |", "|---|---|---|---|---|---|"]
+    for name, cs in per.items():
+        if "FETCH_SIZE" not in cs or "WRITE_SIZE" not in cs:
+            continue
+        fk, nf, ff = cs["FETCH_SIZE"]
+        wk, nw, fw = cs["WRITE_SIZE"]
+        fb, wb = fk * 1024 * ff, wk * 1024 * fw
+        dig = source_digest(KERNEL_SYMBOLS[name][1])
+        out["kernels"][name] = dict(fetch_bytes=round(fb), write_bytes=round(wb),
+                                    total_bytes=round(fb + wb), dispatches=min(nf, nw),
+                                    digest=dig)
+        lines.append(f"| {name} | {min(nf, nw)} | {fk:.0f} | {wk:.0f} | {fb + wb:.4g} | {dig} |")
+    lines += ["", "Medians over dispatches.  Machine-readable copy:", "",
+              "traffic-json: " + json.dumps(out)]
+    return "\n".join(lines)
+
+
+def traffic_of(name):
+    """Scaled HBM bytes per launch of a kernel, or None if absent or the source changed."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            line = [x for x in fh.read().splitlines() if x.startswith("traffic-json: ")][0]
+        rec = json.loads(line[len("traffic-json: "):])["kernels"][name]
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+    if rec["digest"] != source_digest(KERNEL_SYMBOLS[name][1]):
+        return None
+    return rec
+
+
+def summarize_trace(d, command):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run (per-kernel statistics)."""
+    import csv
+    import glob
+    path = os.path.join(d, "run_kernel_stats.csv")
+    if not os.path.exists(path):
+        path = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)[0]
+    with open(path) as fh:
+        rows = list(csv.DictReader(fh))
+    lines = ["# Kernel trace: " + os.path.basename(os.path.normpath(d)), "",
+             "Command (from the repository root):", "", "```", command, "```", "",
+             "Library kernels (namespace `tsv`), all calls in the run (warm-up, timed and "
+             "checking calls):", "",
+             "| kernel | calls | total ms | average us | min us | max us |",
+             "|---|---|---|---|---|---|"]
+    other_ms, other_calls = 0.0, 0
+    for r in rows:
+        name = r["Name"].split("(")[0]
+        if "tsv::" not in name:
+            other_ms += float(r["TotalDurationNs"]) / 1e6
+            other_calls += int(r["Calls"])
+            continue
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} |")
+    lines += ["", f"Other kernels (torch and ROCm libraries: generating the synthetic matrices "
+                  f"and the accuracy checks, outside the timed region): {other_calls} calls, "
+                  f"{other_ms:.1f} ms."]
+    return "\n".join(lines)
+
+
 def roofline_of(kernels):
     name = max(kernels, key=lambda k: kernels[k]["total_ms"])
     kd = kernels[name]
     dt = kd["mfma_dtype"]
+    tr = traffic_of(name) if name in KERNEL_SYMBOLS else None
+    tr_bytes = tr["total_bytes"] if tr else None
+    if tr:
+        tr = dict(fetch_bytes=tr["fetch_bytes"], write_bytes=tr["write_bytes"],
+                  ratio_to_algorithmic=round(tr["total_bytes"] / kd["alg_bytes"], 4),
+                  source=os.path.relpath(TRAFFIC_PROFILE, HERE))
     # HBM bound if the kernel's flops per algorithmic byte are below the ridge of its dtype
     ai = kd["tflops"] * 1e12 / (kd["gbs"] * 1e9)
     ridge = PEAK_TFLOPS[dt] * 1e12 / (HBM_PEAK_GBS * 1e9)
     if ai < ridge:
         return {"bound": "hbm", "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4), "traffic": tr_bytes,
+                "traffic_detail": tr, "kernel": name,
                 "avg_ms": kd["avg_ms"], "launches": kd["launches"],
                 "alg_bytes_per_launch": kd["alg_bytes"]}
     return {"bound": "mfma", "achieved": kd["tflops"], "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
-            "frac": round(kd["tflops"] / PEAK_TFLOPS[dt], 4), "traffic": None, "kernel": name,
+            "frac": round(kd["tflops"] / PEAK_TFLOPS[dt], 4), "traffic": tr_bytes,
+            "traffic_detail": tr, "kernel": name,
             "avg_ms": kd["avg_ms"], "launches": kd["launches"], "mfma_dtype": dt,
             "alg_bytes_per_launch": kd["alg_bytes"], "hbm_gbs": kd["gbs"]}
 
@@ -247,7 +381,20 @@ def main():
                          "calibration for the HBM traffic figures)")
     ap.add_argument("--simple-data", action="store_true",
                     help="Gaussian matrices instead of planted spectra (hardware-counter runs)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the traffic profile from two rocprofv3 --pmc output folders "
+                         "(FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="print a summary of a rocprofv3 --kernel-trace --stats folder and exit")
+    ap.add_argument("--command", default="",
+                    help="the profiling command, recorded in a summary")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.command))
+        return
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace, args.command))
+        return
     global SIMPLE_DATA
     SIMPLE_DATA = args.simple_data
     if args.gpus != 1:
