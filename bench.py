@@ -375,7 +375,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--legs", default="w1,w2,w3,w5")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=100_000)
+    ap.add_argument("--cpu-rows", type=int, default=250_000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB read + 1 GiB write elementwise kernel first (counter "
                          "calibration for the HBM traffic figures)")
