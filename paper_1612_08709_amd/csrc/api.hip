@@ -71,6 +71,55 @@ __global__ void k_ortho_gate(const double* __restrict__ G, int k, int mode, doub
   }
 }
 
+// Intermediate bases of the subspace iteration (Algorithm 5 before its last step) enter
+// only through products with A, and Q = Y R^-1 spans the same space as the TSQR's
+// Householder Q (the paper's own TSQR formed Q = A R^-1).  With T = R^-1 the m x l basis
+// need not be formed by the reverse Householder pass.  Rounding in Y R^-1 grows with
+// kappa(R); when the Frobenius estimate ||R||_F ||R^-1||_F exceeds kappa_max (or R^-1 is
+// not finite, e.g. for a rank-deficient sketch) the kernel sets *use_q = 1 and T = I, and
+// the gated Householder apply forms Q explicitly.  One workgroup; thread c solves
+// R t = e_c by back substitution for column c of T (staged in LDS, written row-major).
+__global__ __launch_bounds__(256) void k_rinv_gate(const double* __restrict__ R, int l,
+                                                   double kappa_max, double* __restrict__ T,
+                                                   int* __restrict__ use_q) {
+  extern __shared__ double Ts[];  // l x l, column c at Ts[c * l + i]
+  __shared__ double red[2][256];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  double tn = 0.0, rn = 0.0;
+  for (int c = tid; c < l; c += 256) {
+    double* t = Ts + (size_t)c * l;
+    for (int i = c; i >= 0; --i) {
+      double acc = (i == c) ? 1.0 : 0.0;
+      for (int k2 = i + 1; k2 <= c; ++k2) acc = fma(-R[i * l + k2], t[k2], acc);
+      const double ti = acc / R[i * l + i];
+      t[i] = ti;
+      tn = fma(ti, ti, tn);
+      rn = fma(R[i * l + c], R[i * l + c], rn);
+    }
+  }
+  red[0][tid] = tn;
+  red[1][tid] = rn;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[0][tid] += red[0][tid + w];
+      red[1][tid] += red[1][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double kap = sqrt(red[0][0]) * sqrt(red[1][0]);
+    bad = !(kap <= kappa_max);  // also catches NaN / Inf
+    *use_q = bad;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < l * l; idx += 256) {
+    const int i = idx / l, c = idx - i * l;
+    T[idx] = bad ? (i == c ? 1.0 : 0.0) : (i <= c ? Ts[(size_t)c * l + i] : 0.0);
+  }
+}
+
 // T = R diag(S) (n x n), for the second orthonormalization of U = Q2 R2.
 __global__ void k_scale_cols(const double* __restrict__ R, const double* __restrict__ S, int n,
                              double* __restrict__ T, const int* __restrict__ gate) {
@@ -249,7 +298,7 @@ namespace {
 
 struct LowrankWs {
   TsqrPlan pY, pZ;
-  double *X, *Y, *Z, *part, *I, *P, *sig, *W, *Wk, *G, *ortho, *Tq;
+  double *X, *Y, *Z, *Zraw, *Qy, *part, *I, *P, *sig, *W, *Wk, *G, *ortho, *Tq;
   void* pack;
   int* gate;
   size_t bytes;
@@ -265,13 +314,16 @@ LowrankWs lowrank_layout(int64_t m, int64_t n, int k, int l, void* work, bool mi
   w.X = c.take<double>((size_t)n * l);
   w.Y = c.take<double>((size_t)m * l);
   w.Z = c.take<double>((size_t)n * l);
+  w.Zraw = c.take<double>((size_t)n * l);
   size_t np = atq_partials(m, n, l);
   const size_t np2 = atq_partials(m, l, l);
   if (np2 > np) np = np2;
   if (mixed && mixed_partials(m, n, l) > np) np = mixed_partials(m, n, l);
   w.part = c.take<double>(np);
   w.pack = nullptr;
+  w.Qy = nullptr;
   if (mixed) {
+    w.Qy = c.take<double>((size_t)m * l);
     size_t pb = mixed_pack_bytes(m, l);
     if (mixed_pack_bytes(n, l) > pb) pb = mixed_pack_bytes(n, l);
     w.pack = c.take<char>(pb);
@@ -299,6 +351,28 @@ int lowrank_check(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t 
 }
 
 // Orthonormal basis of span(Y) by TSQR, written over Y (m x l).
+// Basis of an intermediate step: factor Y, then either T = R^-1 (Y kept) or, when R is too
+// ill-conditioned, the explicit Householder Q written over Y and T = I (device-side choice).
+constexpr double kKappaMax = 1e6;
+hipError_t basis_via_r(const TsqrPlan& p, double* Y, int l, const double* I, double* T,
+                       int* use_q, hipStream_t s) {
+  hipError_t e = tsqr_factor(p, Y, TSSVD_F64, l, s);
+  if (e != hipSuccess) return e;
+  const size_t lds = (size_t)l * l * sizeof(double);
+  static bool attr_set = false;  // the attribute is per function; setting it twice is harmless
+  if (!attr_set) {
+    e = hipFuncSetAttribute((const void*)k_rinv_gate,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(256), lds, s, tsqr_root(p), l, kKappaMax, T,
+                     use_q);
+  TsqrPlan pq = p;
+  pq.gate = use_q;
+  return tsqr_apply(pq, I, l, Y, l, s);
+}
+
 hipError_t orth_inplace(const TsqrPlan& p, double* Y, int l, const double* I, hipStream_t s) {
   hipError_t e = tsqr_factor(p, Y, TSSVD_F64, l, s);
   if (e != hipSuccess) return e;
@@ -355,22 +429,34 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
     return gemm_ax_mixed(A32, lda, m, n, w.pack, li, w.Y, li, kind, s,
                          last ? TSSVD_PROF_AX_FINAL : TSSVD_PROF_AX_BF16);
   };
-  auto atq = [&](bool last) -> hipError_t {
+  auto atq = [&](const double* Qs, bool last, double* Zout) -> hipError_t {
     if (!mixed)
-      return gemm_atq_f64(A, a_dtype, lda, m, n, w.Y, li, li, w.Z, li, w.part, s, TSSVD_PROF_ATQ);
+      return gemm_atq_f64(A, a_dtype, lda, m, n, Qs, li, li, Zout, li, w.part, s,
+                          TSSVD_PROF_ATQ);
     const int kind = !last ? MIX_BF16 : (f32_final ? MIX_F32_ROWS : MIX_BF16X3);
-    hipError_t e = pack_operand(w.Y, m, li, li, kind, w.pack, s);
+    hipError_t e = pack_operand(Qs, m, li, li, kind, w.pack, s);
     if (e != hipSuccess) return e;
-    return gemm_atq_mixed(A32, lda, m, n, w.pack, li, w.Z, li, w.part, kind, s,
+    return gemm_atq_mixed(A32, lda, m, n, w.pack, li, Zout, li, w.part, kind, s,
                           last ? TSSVD_PROF_ATQ_FINAL : TSSVD_PROF_ATQ_BF16);
   };
-  // Algorithm 5: subspace iteration
+  // Algorithm 5: subspace iteration.  Intermediate bases: Q_j = Y R_j^-1 and
+  // Q~_j = Z R~_j^-1 (or the explicit Householder Q when R is ill-conditioned).  In FP64
+  // the product uses Y itself, A^* Q_j = (A^* Y) R_j^-1; in mixed precision Q_j is formed
+  // first, because bfloat16 rounding of Y's entries would be amplified by R_j^-1.
+  int* use_q = w.gate + 1;
   TRY(ax(w.X, q == 0));                                                        // A Q~_0
   for (int64_t j = 0; j < q; ++j) {
-    TRY(orth_inplace(w.pY, w.Y, li, w.I, s));                                  // Q_j
-    TRY(atq(false));                                                           // A^* Q_j
-    TRY(orth_inplace(w.pZ, w.Z, li, w.I, s));                                  // Q~_j
-    TRY(ax(w.Z, j == q - 1));                                                  // A Q~_j
+    TRY(basis_via_r(w.pY, w.Y, li, w.I, w.Tq, use_q, s));                      // Q_j = Y T
+    if (mixed) {
+      TRY(gemm_ax_f64(w.Y, TSSVD_F64, l, m, l, w.Tq, li, li, w.Qy, li, s));   // Q_j
+      TRY(atq(w.Qy, false, w.Z));                                              // A^* Q_j
+    } else {
+      TRY(atq(w.Y, false, w.Zraw));                                            // A^* Y
+      TRY(gemm_ax_f64(w.Zraw, TSSVD_F64, l, n, l, w.Tq, li, li, w.Z, li, s)); // A^* Q_j
+    }
+    TRY(basis_via_r(w.pZ, w.Z, li, w.I, w.Tq, use_q, s));                      // Q~_j = Z T
+    TRY(gemm_ax_f64(w.Z, TSSVD_F64, l, n, l, w.Tq, li, li, w.X, li, s));
+    TRY(ax(w.X, j == q - 1));                                                  // A Q~_j
   }
   TRY(orth_inplace(w.pY, w.Y, li, w.I, s));                                    // Q
   if (o.ortho != TSSVD_ORTHO_ONCE) {
@@ -385,7 +471,7 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   }
   // Algorithm 6: B = Q^* A via B^* = A^* Q = Q_B R_B;  R_B^T = P S W^T  =>
   //   B = P S (Q_B W)^T,  U = Q P_k,  V = Q_B W_k.
-  TRY(atq(true));                                                              // B^* = A^* Q
+  TRY(atq(w.Y, true, w.Z));                                                    // B^* = A^* Q
   TRY(tsqr_factor(w.pZ, w.Z, TSSVD_F64, l, s));
   TRY(jacobi_svd(tsqr_root(w.pZ), li, li, 1, 0.0, o.max_jacobi_sweeps, 0, w.P, w.sig, w.W,
                  info, s));

@@ -29,7 +29,8 @@ struct Carver {
 struct TsqrPlan {
   int64_t m = 0;
   int n = 0;
-  int nc = 0, nr = 0, B = 0;
+  int nc = 0, nr = 0, B = 0;  // leaf column tile, leaf rows per thread, leaf block rows
+  int tnr = 0, BT = 0;        // merge-node rows per thread and block rows
   int64_t nblocks = 0;
   int W = 0;             // leaf workgroups
   int bpw = 0;           // blocks per leaf workgroup
@@ -39,14 +40,15 @@ struct TsqrPlan {
   double* Vleaf = nullptr;  // nblocks * n * B   reflector tails, column-major per block
   double* tauleaf = nullptr;  // nblocks * n
   std::vector<double*> Rlev;  // per level: cnt[L] * n * n
-  std::vector<double*> Vtree; // per level L (merges producing level L+1): cnt[L+1] * n * B
+  std::vector<double*> Vtree; // per level L (merges producing level L+1): cnt[L+1] * n * BT
   std::vector<double*> tautree;
   std::vector<double*> Slev;  // seeds per level: cnt[L] * n * n
   // When non-NULL, every kernel of the plan returns at once if *gate == 0 (device flag).
   const int* gate = nullptr;
 };
 
-TsqrPlan tsqr_plan(int64_t m, int n);
+// nr (8 or 16, narrow tiles only) and wtarget (leaf workgroups) override the defaults.
+TsqrPlan tsqr_plan(int64_t m, int n, int nr = 0, int wtarget = 0);
 void tsqr_carve(TsqrPlan& p, Carver& c);
 // Factor: leaf blocks + tree.  After it, root R (n x n, upper, row-major) is tsqr_root(p).
 hipError_t tsqr_factor(const TsqrPlan& p, const void* A, int a_dtype, int64_t lda,

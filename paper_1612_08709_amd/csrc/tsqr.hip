@@ -345,29 +345,33 @@ __global__ __launch_bounds__(256) void k_leaf_apply(const double* __restrict__ V
 
 // ------------------------------------------------------------------------- host side
 
-static void pick_tile(int n, int& nc, int& nr) {
-  if (n <= 16) { nc = 1; nr = 16; }
-  else if (n <= 32) { nc = 2; nr = 16; }
-  else if (n <= 64) { nc = 4; nr = 16; }
-  else { nc = 8; nr = 8; }
+// Column tile: thread (rg, cg) owns columns cg + 16c, c < NC.  Leaf blocks have B = 16*NR
+// rows; merge nodes use blocks of BT = 16*TNR rows.
+static void pick_tile(int n, int& nc, int& nr, int& tnr) {
+  if (n <= 16) { nc = 1; nr = 16; tnr = 16; }
+  else if (n <= 32) { nc = 2; nr = 16; tnr = 16; }
+  else if (n <= 64) { nc = 4; nr = 16; tnr = 16; }
+  else { nc = 8; nr = 8; tnr = 8; }
 }
 
-TsqrPlan tsqr_plan(int64_t m, int n) {
+TsqrPlan tsqr_plan(int64_t m, int n, int nr, int wtarget) {
   TsqrPlan p;
   p.m = m;
   p.n = n;
-  pick_tile(n, p.nc, p.nr);
+  pick_tile(n, p.nc, p.nr, p.tnr);
+  if ((nr == 8 || nr == 16) && p.nc <= 4) p.nr = nr;
   p.B = 16 * p.nr;
+  p.BT = 16 * p.tnr;
   p.nblocks = (m + p.B - 1) / p.B;
   // About as many leaf workgroups as can be resident at once (two per CU for the wide
   // tiles, four for the narrow ones): fewer would idle CUs, more would only deepen the
   // merge tree.
-  const int64_t target = (p.nc >= 4) ? 512 : 1024;
+  const int64_t target = wtarget > 0 ? wtarget : (p.nc >= 4) ? 512 : 1024;
   int64_t W = p.nblocks < target ? p.nblocks : target;
   p.bpw = (int)((p.nblocks + W - 1) / W);
   p.W = (int)((p.nblocks + p.bpw - 1) / p.bpw);
-  // merge nodes stack G = B / n child factors in one block: fan-in G + 1
-  p.G = p.B / n;
+  // merge nodes stack G = BT / n child factors in one block: fan-in G + 1
+  p.G = p.BT / n;
   p.cnt.clear();
   p.cnt.push_back(p.W);
   while (p.cnt.back() > 1) p.cnt.push_back((p.cnt.back() + p.G) / (p.G + 1));
@@ -388,14 +392,14 @@ void tsqr_carve(TsqrPlan& p, Carver& c) {
     p.Slev[l] = c.take<double>((size_t)p.cnt[l] * n * n);
   }
   for (int l = 0; l + 1 < L; ++l) {
-    p.Vtree[l] = c.take<double>((size_t)p.cnt[l + 1] * n * p.B);
+    p.Vtree[l] = c.take<double>((size_t)p.cnt[l + 1] * n * p.BT);
     p.tautree[l] = c.take<double>((size_t)p.cnt[l + 1] * n);
   }
 }
 
 double* tsqr_root(const TsqrPlan& p) { return p.Rlev.back(); }
 
-template <int NC, int NR>
+template <int NC, int NR, int TNR>
 static hipError_t factor_impl(const TsqrPlan& p, const void* A, int a_dtype, int64_t lda,
                               hipStream_t s, bool prof) {
   const int n = p.n;
@@ -410,14 +414,15 @@ static hipError_t factor_impl(const TsqrPlan& p, const void* A, int a_dtype, int
                        (const float*)A, lda, p.m, n, p.bpw, p.nblocks, p.Vleaf, p.tauleaf,
                        p.Rlev[0], p.gate);
   if (prof) prof_end(TSSVD_PROF_LEAF_FACTOR, s);
+  const size_t lds_t = (size_t)(tri_size(n) + 2 * 16 * TNR + n) * sizeof(double);
   for (size_t l = 0; l + 1 < p.cnt.size(); ++l)
-    hipLaunchKernelGGL((k_tree_factor<NC, NR>), dim3(p.cnt[l + 1]), dim3(256), lds, s,
+    hipLaunchKernelGGL((k_tree_factor<NC, TNR>), dim3(p.cnt[l + 1]), dim3(256), lds_t, s,
                        p.Rlev[l], p.cnt[l], n, p.G, p.Rlev[l + 1], p.Vtree[l], p.tautree[l],
                        p.gate);
   return hipGetLastError();
 }
 
-template <int NC, int NR>
+template <int NC, int NR, int TNR>
 static hipError_t apply_impl(const TsqrPlan& p, const double* S, int k, double* out,
                              int64_t ldo, hipStream_t s, bool prof) {
   const int n = p.n;
@@ -427,7 +432,7 @@ static hipError_t apply_impl(const TsqrPlan& p, const double* S, int k, double* 
   if (e != hipSuccess) return e;
   const size_t lds = (size_t)n * k * sizeof(double);
   for (int l = L - 2; l >= 0; --l)
-    hipLaunchKernelGGL((k_tree_apply<NC, NR>), dim3(p.cnt[l + 1]), dim3(256), lds, s,
+    hipLaunchKernelGGL((k_tree_apply<NC, TNR>), dim3(p.cnt[l + 1]), dim3(256), lds, s,
                        p.Slev[l + 1], p.cnt[l], n, k, p.G, p.Vtree[l], p.tautree[l],
                        p.Slev[l], p.gate);
   if (prof) prof_begin(TSSVD_PROF_LEAF_APPLY, s);
@@ -439,21 +444,29 @@ static hipError_t apply_impl(const TsqrPlan& p, const double* S, int k, double* 
 
 hipError_t tsqr_factor(const TsqrPlan& p, const void* A, int a_dtype, int64_t lda,
                        hipStream_t s, bool prof) {
-  switch (p.nc) {
-    case 1: return factor_impl<1, 16>(p, A, a_dtype, lda, s, prof);
-    case 2: return factor_impl<2, 16>(p, A, a_dtype, lda, s, prof);
-    case 4: return factor_impl<4, 16>(p, A, a_dtype, lda, s, prof);
-    default: return factor_impl<8, 8>(p, A, a_dtype, lda, s, prof);
+  switch (p.nc * 100 + p.nr) {
+    case 116: return factor_impl<1, 16, 16>(p, A, a_dtype, lda, s, prof);
+    case 108: return factor_impl<1, 8, 16>(p, A, a_dtype, lda, s, prof);
+    case 216: return factor_impl<2, 16, 16>(p, A, a_dtype, lda, s, prof);
+    case 208: return factor_impl<2, 8, 16>(p, A, a_dtype, lda, s, prof);
+    case 416: return factor_impl<4, 16, 16>(p, A, a_dtype, lda, s, prof);
+    case 408: return factor_impl<4, 8, 16>(p, A, a_dtype, lda, s, prof);
+    case 808: return factor_impl<8, 8, 8>(p, A, a_dtype, lda, s, prof);
+    default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t tsqr_apply(const TsqrPlan& p, const double* S, int k, double* out, int64_t ldo,
                       hipStream_t s, bool prof) {
-  switch (p.nc) {
-    case 1: return apply_impl<1, 16>(p, S, k, out, ldo, s, prof);
-    case 2: return apply_impl<2, 16>(p, S, k, out, ldo, s, prof);
-    case 4: return apply_impl<4, 16>(p, S, k, out, ldo, s, prof);
-    default: return apply_impl<8, 8>(p, S, k, out, ldo, s, prof);
+  switch (p.nc * 100 + p.nr) {
+    case 116: return apply_impl<1, 16, 16>(p, S, k, out, ldo, s, prof);
+    case 108: return apply_impl<1, 8, 16>(p, S, k, out, ldo, s, prof);
+    case 216: return apply_impl<2, 16, 16>(p, S, k, out, ldo, s, prof);
+    case 208: return apply_impl<2, 8, 16>(p, S, k, out, ldo, s, prof);
+    case 416: return apply_impl<4, 16, 16>(p, S, k, out, ldo, s, prof);
+    case 408: return apply_impl<4, 8, 16>(p, S, k, out, ldo, s, prof);
+    case 808: return apply_impl<8, 8, 8>(p, S, k, out, ldo, s, prof);
+    default: return hipErrorInvalidValue;
   }
 }
 
