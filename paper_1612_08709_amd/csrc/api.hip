@@ -77,27 +77,54 @@ __global__ void k_ortho_gate(const double* __restrict__ G, int k, int mode, doub
 // need not be formed by the reverse Householder pass.  Rounding in Y R^-1 grows with
 // kappa(R); when the Frobenius estimate ||R||_F ||R^-1||_F exceeds kappa_max (or R^-1 is
 // not finite, e.g. for a rank-deficient sketch) the kernel sets *use_q = 1 and T = I, and
-// the gated Householder apply forms Q explicitly.  One workgroup; thread c solves
-// R t = e_c by back substitution for column c of T (staged in LDS, written row-major).
+// the gated Householder apply forms Q explicitly.  One workgroup computes T row by row
+// from the bottom (back substitution for all columns at once; R and T packed in LDS).
+__device__ __forceinline__ int upper_idx(int i, int c, int l) {
+  return i * l - ((i * (i - 1)) >> 1) + (c - i);  // packed upper triangle, row-major
+}
+
 __global__ __launch_bounds__(256) void k_rinv_gate(const double* __restrict__ R, int l,
                                                    double kappa_max, double* __restrict__ T,
                                                    int* __restrict__ use_q) {
-  extern __shared__ double Ts[];  // l x l, column c at Ts[c * l + i]
+  extern __shared__ double sm[];  // packed upper triangles: R, then T = R^-1
+  const int np = l * (l + 1) / 2;
+  double* Rs = sm;
+  double* Ts = sm + np;
   __shared__ double red[2][256];
   __shared__ int bad;
   const int tid = threadIdx.x;
-  double tn = 0.0, rn = 0.0;
-  for (int c = tid; c < l; c += 256) {
-    double* t = Ts + (size_t)c * l;
-    for (int i = c; i >= 0; --i) {
-      double acc = (i == c) ? 1.0 : 0.0;
-      for (int k2 = i + 1; k2 <= c; ++k2) acc = fma(-R[i * l + k2], t[k2], acc);
-      const double ti = acc / R[i * l + i];
-      t[i] = ti;
-      tn = fma(ti, ti, tn);
-      rn = fma(R[i * l + c], R[i * l + c], rn);
+  double rn = 0.0;
+  for (int idx = tid; idx < l * l; idx += 256) {
+    const int i = idx / l, c = idx - i * l;
+    if (c >= i) {
+      const double r = R[idx];
+      Rs[upper_idx(i, c, l)] = r;
+      rn = fma(r, r, rn);
     }
   }
+  __syncthreads();
+  // rows of T bottom-up: T[i][c] = (delta_ic - sum_{i<k<=c} R[i][k] T[k][c]) / R[i][i].
+  // Each column's sum is split over the four lanes of a quad (k = i+1+q, +4, ...) and
+  // combined with a quad reduction.
+  const int q4 = tid & 3, cq = tid >> 2;
+  for (int i = l - 1; i >= 0; --i) {
+    const double* ri = Rs + upper_idx(i, i, l) - i;  // ri[k] = R[i][k], k >= i
+    for (int c0 = 0; c0 < l; c0 += 64) {
+      const int c = c0 + cq;
+      const bool live = c < l && c >= i;
+      double acc = 0.0;
+      if (live) {
+#pragma unroll 4
+        for (int k2 = i + 1 + q4; k2 <= c; k2 += 4)
+          acc = fma(-ri[k2], Ts[upper_idx(k2, c, l)], acc);
+      }
+      acc = sum4(acc);
+      if (live && q4 == 0) Ts[upper_idx(i, c, l)] = ((c == i ? 1.0 : 0.0) + acc) / ri[i];
+    }
+    __syncthreads();
+  }
+  double tn = 0.0;
+  for (int idx = tid; idx < np; idx += 256) tn = fma(Ts[idx], Ts[idx], tn);
   red[0][tid] = tn;
   red[1][tid] = rn;
   __syncthreads();
@@ -116,7 +143,7 @@ __global__ __launch_bounds__(256) void k_rinv_gate(const double* __restrict__ R,
   __syncthreads();
   for (int idx = tid; idx < l * l; idx += 256) {
     const int i = idx / l, c = idx - i * l;
-    T[idx] = bad ? (i == c ? 1.0 : 0.0) : (i <= c ? Ts[(size_t)c * l + i] : 0.0);
+    T[idx] = bad ? (i == c ? 1.0 : 0.0) : (c >= i ? Ts[upper_idx(i, c, l)] : 0.0);
   }
 }
 
@@ -358,7 +385,7 @@ hipError_t basis_via_r(const TsqrPlan& p, double* Y, int l, const double* I, dou
                        int* use_q, hipStream_t s) {
   hipError_t e = tsqr_factor(p, Y, TSSVD_F64, l, s);
   if (e != hipSuccess) return e;
-  const size_t lds = (size_t)l * l * sizeof(double);
+  const size_t lds = (size_t)l * (l + 1) * sizeof(double);
   static bool attr_set = false;  // the attribute is per function; setting it twice is harmless
   if (!attr_set) {
     e = hipFuncSetAttribute((const void*)k_rinv_gate,

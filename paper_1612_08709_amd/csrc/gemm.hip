@@ -249,8 +249,18 @@ __global__ void k_reduce_chunks(const double* __restrict__ part, int nchunk, int
                                 double* __restrict__ Z, int l, int ldz) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= count) return;
+  // chunk order is fixed (bitwise reproducible); the loads of eight chunks are issued
+  // before their additions so the latency of one does not serialize the next
   double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * count + idx];
+  int c = 0;
+  for (; c + 8 <= nchunk; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = part[(int64_t)(c + j) * count + idx];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += v[j];
+  }
+  for (; c < nchunk; ++c) s += part[(int64_t)c * count + idx];
   const int64_t row = idx / l;
   const int col = (int)(idx - row * l);
   Z[row * ldz + col] = s;

@@ -54,6 +54,25 @@ def test_exact_rank_recovers_planted_sigma():
     assert sigma_rel(host(S), sigma[:k]) < 1e-12
 
 
+@pytest.mark.parametrize("q", [1, 2])
+def test_rank_below_sketch_width(q):
+    """rank(A) = 6 < l = 12: R of every sketch is singular, so the intermediate bases take
+    the explicit Householder path; the top k <= rank triplets still match the oracle."""
+    m, n, r, k, l = 3000, 300, 6, 5, 12
+    A = sm.planted(m, n, np.linspace(1.0, 0.3, r), workload=64)
+    Om = sm.sketch(n, l, 64)
+    _compare(A, Om, k, q)
+
+
+def test_ill_conditioned_sketch():
+    """sigma_j = 10^(-0.45 (j-1)): sigma_16 / sigma_1 ~ 2e-7, so ||R||_F ||R^-1||_F exceeds
+    the threshold of the R^-1 basis and the Householder basis is used; parity as usual."""
+    m, n, k, l = 4000, 200, 8, 16
+    sig = 10.0 ** (-0.45 * np.arange(n))
+    A = sm.planted(m, n, sig, workload=65)
+    _compare(A, sm.sketch(n, l, 65), k, 2)
+
+
 def test_device_philox_sketch_matches_oracle_generator():
     """Omega = NULL: the sketch comes from Philox4x32-10 on the device (seeded)."""
     m, n, k, l, q = 3000, 500, 10, 16, 1
