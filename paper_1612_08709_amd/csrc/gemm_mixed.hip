@@ -136,8 +136,8 @@ __device__ __forceinline__ bool aligned16(const void* p) {
 // (i = lane%16, g = lane/16) reads A[row][32kb + 8g .. 32kb + 8g + 7] (two 16-byte loads
 // when VEC: A 16-byte aligned and lda a multiple of 4).  The main loop runs over the full
 // steps with no bounds tests (rows past m read row m-1 and are not stored); a ragged last
-// step reads with tests.  The A (and, for one piece, X) fragments of step kb+1 are loaded
-// before the products of step kb.
+// step reads with tests.  The A and X fragments of step kb+1 are loaded before the
+// products of step kb.
 template <int PIECES>
 __device__ __forceinline__ void to_pieces(float x, __bf16 (&p)[3]) {
   if (PIECES == 1) {
@@ -181,7 +181,6 @@ __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, in
                                                  int64_t m, int n,
                                                  const bf16x8* __restrict__ Xp, int64_t nfrag,
                                                  int l, double* __restrict__ Y, int ldy) {
-  constexpr bool PREB = (PIECES == 1);  // prefetch X fragments too (registers allow it)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int64_t rbase = (int64_t)blockIdx.x * (64 * RT) + (int64_t)wave * (16 * RT);
@@ -229,30 +228,25 @@ __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, in
     bf16x8 b0[PIECES][NT], b1[PIECES][NT];
     const int last = nfull - 1;
     load_a(0, v0);
-    if (PREB) load_b(0, b0);
+    load_b(0, b0);
     load_a(last < 1 ? last : 1, v1);
-    if (PREB) load_b(last < 1 ? last : 1, b1);
+    load_b(last < 1 ? last : 1, b1);
     int kb = 0;
     for (; kb + 2 <= nfull; kb += 2) {
-      if (!PREB) load_b(kb, b0);
       ax_products<RT, NT, PIECES>(v0, b0, acc);
       __builtin_amdgcn_sched_barrier(0);
       const int k2 = (kb + 2 < last) ? kb + 2 : last;
       load_a(k2, v0);
-      if (PREB) load_b(k2, b0);
+      load_b(k2, b0);
       __builtin_amdgcn_sched_barrier(0);
-      if (!PREB) load_b(kb + 1, b1);
       ax_products<RT, NT, PIECES>(v1, b1, acc);
       __builtin_amdgcn_sched_barrier(0);
       const int k3 = (kb + 3 < last) ? kb + 3 : last;
       load_a(k3, v1);
-      if (PREB) load_b(k3, b1);
+      load_b(k3, b1);
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (kb < nfull) {
-      if (!PREB) load_b(kb, b0);
-      ax_products<RT, NT, PIECES>(v0, b0, acc);
-    }
+    if (kb < nfull) ax_products<RT, NT, PIECES>(v0, b0, acc);
   }
   if ((nfull << 5) < n) {
     // ragged last step: columns past n read as 0 (the packed X rows there are 0 as well)
@@ -398,7 +392,6 @@ __device__ __forceinline__ void atq_rows(const float* __restrict__ A, int64_t ld
                                          int cb, int g, int64_t r0, int64_t r1,
                                          const bf16x8* __restrict__ qp, int64_t nfrag,
                                          f32x4 (&acc)[4][NT]) {
-  constexpr bool PREB = (PIECES == 1);
   auto load_a = [&](int64_t rb, float (&v)[8][4]) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
@@ -426,31 +419,26 @@ __device__ __forceinline__ void atq_rows(const float* __restrict__ A, int64_t ld
     bf16x8 b0[PIECES][NT], b1[PIECES][NT];
     const int64_t last = rfull - 32;
     load_a(r0, v0);
-    if (PREB) load_b(r0, b0);
+    load_b(r0, b0);
     const int64_t r1st = (r0 + 32 < last) ? r0 + 32 : last;
     load_a(r1st, v1);
-    if (PREB) load_b(r1st, b1);
+    load_b(r1st, b1);
     int64_t rb = r0;
     for (; rb + 64 <= rfull; rb += 64) {
-      if (!PREB) load_b(rb, b0);
       atq_products<NT, PIECES>(v0, b0, acc);
       __builtin_amdgcn_sched_barrier(0);
       const int64_t r2 = (rb + 64 < last) ? rb + 64 : last;
       load_a(r2, v0);
-      if (PREB) load_b(r2, b0);
+      load_b(r2, b0);
       __builtin_amdgcn_sched_barrier(0);
-      if (!PREB) load_b(rb + 32, b1);
       atq_products<NT, PIECES>(v1, b1, acc);
       __builtin_amdgcn_sched_barrier(0);
       const int64_t r3 = (rb + 96 < last) ? rb + 96 : last;
       load_a(r3, v1);
-      if (PREB) load_b(r3, b1);
+      load_b(r3, b1);
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (rb < rfull) {
-      if (!PREB) load_b(rb, b0);
-      atq_products<NT, PIECES>(v0, b0, acc);
-    }
+    if (rb < rfull) atq_products<NT, PIECES>(v0, b0, acc);
   }
   if (rfull < r1) {
     // ragged last rows (only the chunk that ends at m): rows past r1 read as 0
