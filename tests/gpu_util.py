@@ -40,3 +40,43 @@ def col_sin(U, Ur):
 
 def flush_print(*a):
     print(*a, flush=True)
+
+
+def ortho_gpu(U):
+    """||U^T U - I||_2 in float64 on the device."""
+    G = U.T @ U
+    G -= torch.eye(G.shape[0], dtype=G.dtype, device=G.device)
+    return float(torch.linalg.matrix_norm(G, ord=2))
+
+
+def residual_gpu(A, U, S, V, tol=1e-10, max_iters=400, seed=12345, chunk=50_000):
+    """Power-method estimate of ||A - U diag(S) V^T||_2 for a large device matrix A.
+
+    Same iteration as the oracle's checker (E x applied implicitly as A x - U (S (V^T x)),
+    continued until the estimate changes by less than ``tol`` relatively), with the
+    products A x and A^T y done in float64 on the device over row chunks of A.
+    """
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    n = A.shape[1]
+    x = torch.randn(n, generator=g, dtype=torch.float64).to(A.device)
+    x /= torch.linalg.norm(x)
+
+    def a_mul(x):
+        return torch.cat([A[r0:r0 + chunk].double() @ x for r0 in range(0, A.shape[0], chunk)])
+
+    def at_mul(y):
+        z = torch.zeros(n, dtype=torch.float64, device=A.device)
+        for r0 in range(0, A.shape[0], chunk):
+            z += A[r0:r0 + chunk].double().T @ y[r0:r0 + chunk]
+        return z
+
+    est = 0.0
+    for it in range(max_iters):
+        y = a_mul(x) - U @ (S * (V.T @ x))
+        z = at_mul(y) - V @ (S * (U.T @ y))
+        new = float(torch.sqrt(torch.linalg.norm(z)))
+        x = z / torch.linalg.norm(z)
+        if it > 0 and abs(new - est) <= tol * new:
+            return new
+        est = new
+    return est

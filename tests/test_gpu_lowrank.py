@@ -31,7 +31,7 @@ def _compare(A, Om, k, q, dtype=torch.float64, s_tol=1e-11, v_tol=1e-8, **kw):
 
 @pytest.mark.parametrize("m,n,k,l,q", [(3000, 400, 20, 30, 2), (1000, 37, 5, 8, 0),
                                        (4097, 1000, 16, 24, 2), (2500, 700, 50, 60, 3),
-                                       (600, 500, 10, 10, 1)])
+                                       (600, 500, 10, 10, 1), (6000, 700, 100, 100, 1)])
 def test_small_vs_oracle(m, n, k, l, q):
     flush_print("case lowrank", m, n, k, l, q)
     A = sm.planted(m, n, 1.0 / np.arange(1, min(m, n) + 1), workload=50 + l)

@@ -14,7 +14,7 @@ from oracle import checks
 from oracle.lowrank_ref import lowrank_ref
 from synth import matrices as sm
 
-from gpu_util import col_sin, dev, flush_print, host, sigma_rel
+from gpu_util import col_sin, dev, flush_print, host, ortho_gpu, residual_gpu, sigma_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -92,3 +92,35 @@ def test_f32_mfma_final_flag_same_result_class():
     eb = checks.spectral_residual(A64, host(b[0]), host(b[1]), host(b[2]), tol=1e-9)
     assert abs(ea - eb) <= 1e-6 * host(a[1])[0]
     assert sigma_rel(host(a[1]), host(b[1])) < 1e-5
+
+
+def test_workload4_full_size():
+    """500,000 x 8,000 float32 (16 GB), sigma_j = exp(-j/15) (j <= 600) + 1e-5 noise, k=50,
+    l=60, q=3, in the launch configuration the benchmark times.  Properties that hold at
+    any size: orthonormality of U and V (<= 1e-12), sigma within 1e-6 of the all-FP64 GPU
+    path on the same bytes and sketch, the spectral residual within 1e-6 sigma_1 of the
+    FP64 path's, and the leading sigma near the planted ones (the noise moves them by
+    about ||N||_2^2 / sigma_j, ||N||_2 ~ 7e-3)."""
+    from synth import torch_gen
+    spec = sm.workload_spec(4)
+    m, n, k, l, q = spec["m"], spec["n"], spec["k"], spec["l"], spec["q"]
+    flush_print("case workload4 generate")
+    A = torch_gen.planted(m, n, spec["sigma"], 4, "cuda:0", noise=spec.get("noise", 0.0),
+                          dtype=torch.float32, rank=spec.get("rank"))
+    Om = torch_gen.sketch(n, l, 4, "cuda:0")
+    flush_print("case workload4 mixed")
+    Um, Sm, Vm, _ = T.lowrank_svd(A, k, l, q, Om, prec=T.PREC_MIXED)
+    flush_print("case workload4 fp64")
+    Uf, Sf, Vf, _ = T.lowrank_svd(A, k, l, q, Om, prec=T.PREC_FP64)
+    torch.cuda.synchronize()
+    assert ortho_gpu(Um) <= 1e-12 and ortho_gpu(Vm) <= 1e-12
+    assert ortho_gpu(Uf) <= 1e-13 and ortho_gpu(Vf) <= 1e-13
+    sm_, sf_ = host(Sm), host(Sf)
+    assert np.all(np.diff(sm_) <= 0)
+    assert sigma_rel(sm_, sf_) <= 1e-6
+    assert sigma_rel(sm_[:10], np.asarray(spec["sigma"])[:10]) <= 1e-3
+    flush_print("case workload4 residuals")
+    em = residual_gpu(A, Um, Sm, Vm)
+    ef = residual_gpu(A, Uf, Sf, Vf)
+    flush_print(f"  residual mixed {em:.9e} fp64 {ef:.9e} diff {abs(em - ef):.2e}")
+    assert abs(em - ef) <= 1e-6 * sf_[0]
