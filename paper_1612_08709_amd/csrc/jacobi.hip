@@ -63,6 +63,7 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(
   }
 
   const double tol = sqrt((double)n) * DBL_EPSILON;
+  const double tol2 = tol * tol;
   const int np = (n + 1) & ~1;  // players in the circle method
   int sweep = 0;
   bool converged = (n < 2);
@@ -93,10 +94,14 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(
           al = sum16(al);
           be = sum16(be);
           ga = sum16(ga);
-          if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
-            const double c = 1.0 / sqrt(fma(tt, tt, 1.0));
+          // rotate when |ga| > tol sqrt(al be), tested on squares (no square roots).
+          // tan(theta) = 2 ga sign(d) / (|d| + sqrt(d^2 + 4 ga^2)), d = be - al: the smaller
+          // root of t^2 + 2 zeta t - 1 = 0 with zeta = d / (2 ga), one division.
+          if (ga != 0.0 && ga * ga > tol2 * al * be) {
+            const double d = be - al;
+            const double g2 = 2.0 * ga;
+            const double tt = (d >= 0.0 ? g2 : -g2) / (fabs(d) + sqrt(fma(d, d, g2 * g2)));
+            const double c = rsqrt(fma(tt, tt, 1.0));
             const double s = c * tt;
             for (int i = lane16; i < n; i += 16) {
               const double x = mp[i], y = mq[i];
