@@ -65,15 +65,27 @@ def time_calls(fn, steps, warmup):
 
 
 # per-kernel model: algorithmic bytes and flops of one launch, and the bound it is priced at
-def kernel_model(name, m, n, l, a_bytes_per_elem):
+def kernel_model(name, m, n, l, a_bytes_per_elem, a_copy=False):
+    """Algorithmic bytes and flops of one launch.  a_copy: the mixed power steps keep a
+    bfloat16 copy of A (written by the first pass, read by ax_bf16c / atq_bf16c)."""
     L = 16 * ((l + 15) // 16)
     abytes = m * n * a_bytes_per_elem
+    cbytes = m * (32 * ((n + 31) // 32)) * 2  # the bfloat16 copy (columns padded to 32)
     flops = 2.0 * m * n * l
     if name in ("gemm_ax_f64", "gemm_atq_f64"):
         return dict(alg_bytes=abytes + 8 * (m * l + n * l), flops=flops, dtype="f64")
-    if name in ("ax_bf16", "atq_bf16"):
-        return dict(alg_bytes=abytes + 2 * (m * l if "atq" in name else n * l) +
-                    8 * (n * l if "atq" in name else m * l), flops=2.0 * m * n * L, dtype="bf16")
+    if name == "ax_bf16":
+        return dict(alg_bytes=abytes + (cbytes if a_copy else 0) + 2 * n * L + 8 * m * l,
+                    flops=2.0 * m * n * L, dtype="bf16")
+    if name == "atq_bf16":
+        return dict(alg_bytes=abytes + 2 * m * L + 8 * n * l, flops=2.0 * m * n * L,
+                    dtype="bf16")
+    if name == "ax_bf16c":
+        return dict(alg_bytes=cbytes + 2 * n * L + 8 * m * l, flops=2.0 * m * n * L,
+                    dtype="bf16")
+    if name == "atq_bf16c":
+        return dict(alg_bytes=cbytes + 2 * m * L + 8 * n * l, flops=2.0 * m * n * L,
+                    dtype="bf16")
     if name in ("ax_final", "atq_final"):
         # float32-exact inputs as three bfloat16 pieces: six bf16 products per MFMA tile
         return dict(alg_bytes=abytes + 4 * (m * l if "atq" in name else n * l) +
@@ -112,8 +124,9 @@ def run_lowrank(A, spec, prec, steps, warmup, workload):
     U, S, V = call.run(Om)
     torch.cuda.synchronize()
     kernels = {}
+    a_copy = prec == T.PREC_MIXED and q >= 1
     for name, (tot, cnt) in prof.items():
-        mod = kernel_model(name, m, n, l, A.element_size())
+        mod = kernel_model(name, m, n, l, A.element_size(), a_copy)
         avg = tot / cnt / 1e3
         d = dict(total_ms=round(tot, 4), launches=cnt, avg_ms=round(avg * 1e3, 4))
         if mod:
@@ -137,6 +150,8 @@ TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "hbm_traffic_workload4.md")
 KERNEL_SYMBOLS = {  # profile marker name -> (regex on the kernel symbol, source files)
     "ax_bf16": (r"k_ax_bf16<\d+, \d+, 1[,>]", ["gemm_mixed.hip"]),
     "atq_bf16": (r"k_atq_bf16<\d+, 1[,>]", ["gemm_mixed.hip"]),
+    "ax_bf16c": (r"k_ax_bf16c<", ["gemm_mixed.hip"]),
+    "atq_bf16c": (r"k_atq_bf16c<", ["gemm_mixed.hip"]),
     "ax_final": (r"k_ax_bf16<\d+, \d+, 3[,>]", ["gemm_mixed.hip"]),
     "atq_final": (r"k_atq_bf16<\d+, 3[,>]", ["gemm_mixed.hip"]),
     "gemm_ax_f64": (r"k_gemm_ax_f64<\d+, \d+, float>", ["gemm.hip"]),

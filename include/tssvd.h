@@ -89,6 +89,12 @@ typedef struct {
  * default exact three-way bfloat16 split of the float32 inputs (same float32-input result,
  * float32 accumulation either way). */
 #define TSSVD_FLAG_F32_MFMA_FINAL 1
+/* Mixed precision, q >= 1: do not keep a bfloat16 copy of A for the power steps.  By
+ * default the first pass over A also stores A rounded to bfloat16 (m x n rounded up to 32
+ * columns, 2 bytes each, inside the workspace) and the other power-step passes read that
+ * copy instead of the float32 A: half the bytes, bit-identical products.  With this flag
+ * the workspace is smaller by that amount and every pass reads the float32 A. */
+#define TSSVD_FLAG_NO_A_COPY 2
 
 /* Device-side record written (when non-NULL) at the end of every call. */
 typedef struct {
@@ -195,7 +201,9 @@ enum {
   TSSVD_PROF_ATQ_BF16 = 5,     /* Z = A^T Q, bfloat16 inputs (mixed power steps)          */
   TSSVD_PROF_AX_FINAL = 6,     /* Y = A X, float32-exact inputs (mixed final sketch)      */
   TSSVD_PROF_ATQ_FINAL = 7,    /* Z = A^T Q, float32-exact inputs (mixed B = Q^T A)       */
-  TSSVD_PROF_KINDS = 8
+  TSSVD_PROF_AX_BF16C = 8,     /* Y = A X reading the bfloat16 copy of A (mixed)          */
+  TSSVD_PROF_ATQ_BF16C = 9,    /* Z = A^T Q reading the bfloat16 copy of A (mixed)        */
+  TSSVD_PROF_KINDS = 10
 };
 int tssvd_profile_enable(int on);      /* on != 0: start recording (counters reset)      */
 int tssvd_profile_read(int kind, double* total_ms, int64_t* launches);

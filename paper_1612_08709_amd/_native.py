@@ -20,6 +20,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 ORTHO_AUTO, ORTHO_ONCE, ORTHO_TWICE = 0, 1, 2
 NUM_NONFINITE, NUM_NO_CONVERGENCE = 1, 2
 FLAG_F32_MFMA_FINAL = 1
+FLAG_NO_A_COPY = 2
 
 # every exported symbol declared in include/tssvd.h
 EXPORTS = (
@@ -33,8 +34,10 @@ EXPORTS = (
 
 PROF_AX, PROF_ATQ, PROF_LEAF_FACTOR, PROF_LEAF_APPLY = 0, 1, 2, 3
 PROF_AX_BF16, PROF_ATQ_BF16, PROF_AX_FINAL, PROF_ATQ_FINAL = 4, 5, 6, 7
+PROF_AX_BF16C, PROF_ATQ_BF16C = 8, 9
 PROF_NAMES = {0: "gemm_ax_f64", 1: "gemm_atq_f64", 2: "tsqr_leaf_factor", 3: "tsqr_leaf_apply",
-              4: "ax_bf16", 5: "atq_bf16", 6: "ax_final", 7: "atq_final"}
+              4: "ax_bf16", 5: "atq_bf16", 6: "ax_final", 7: "atq_final", 8: "ax_bf16c",
+              9: "atq_bf16c"}
 
 
 class Opts(C.Structure):

@@ -327,11 +327,13 @@ struct LowrankWs {
   TsqrPlan pY, pZ;
   double *X, *Y, *Z, *Zraw, *Qy, *part, *I, *P, *sig, *W, *Wk, *G, *ortho, *Tq;
   void* pack;
+  void* Acopy;  // bfloat16 copy of A for the mixed power steps (or null)
   int* gate;
   size_t bytes;
 };
 
-LowrankWs lowrank_layout(int64_t m, int64_t n, int k, int l, void* work, bool mixed) {
+LowrankWs lowrank_layout(int64_t m, int64_t n, int k, int l, void* work, bool mixed,
+                         bool acopy) {
   LowrankWs w;
   Carver c(work);
   w.pY = tsqr_plan(m, l);
@@ -355,6 +357,7 @@ LowrankWs lowrank_layout(int64_t m, int64_t n, int k, int l, void* work, bool mi
     if (mixed_pack_bytes(n, l) > pb) pb = mixed_pack_bytes(n, l);
     w.pack = c.take<char>(pb);
   }
+  w.Acopy = acopy ? (void*)c.take<char>(bf16_copy_bytes(m, n)) : nullptr;
   const size_t ll = (size_t)l * l;
   w.I = c.take<double>(ll);
   w.P = c.take<double>(ll);
@@ -415,9 +418,9 @@ int lowrank_svd_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t l, int6
   if (!bytes) return TSSVD_E_INVALID_ARG;
   int st = lowrank_check((const void*)1, a_dtype, m, n, n, k, l, q);
   if (st != TSSVD_OK) return st;
-  (void)opts;
   const bool mixed = opts && opts->prec == TSSVD_PREC_MIXED;
-  *bytes = lowrank_layout(m, n, (int)k, (int)l, nullptr, mixed).bytes;
+  const bool acopy = mixed && q >= 1 && !(opts->flags & TSSVD_FLAG_NO_A_COPY);
+  *bytes = lowrank_layout(m, n, (int)k, (int)l, nullptr, mixed, acopy).bytes;
   return TSSVD_OK;
 }
 
@@ -434,7 +437,8 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   if (mixed && a_dtype != TSSVD_F32) return TSSVD_E_INVALID_ARG;
   if (o.working_precision > 0.0) return TSSVD_E_UNSUPPORTED;
   const int ki = (int)k, li = (int)l;
-  LowrankWs w = lowrank_layout(m, n, ki, li, work, mixed);
+  const bool acopy = mixed && q >= 1 && !(o.flags & TSSVD_FLAG_NO_A_COPY);
+  LowrankWs w = lowrank_layout(m, n, ki, li, work, mixed, acopy);
   if (!work || work_bytes < w.bytes) return TSSVD_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
 
@@ -448,13 +452,20 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   // power steps, float32 inputs for the last sketch and for B (the operand is packed first).
   const float* A32 = static_cast<const float*>(A);
   const bool f32_final = (o.flags & TSSVD_FLAG_F32_MFMA_FINAL) != 0;
+  // With the bfloat16 copy, the first power-step pass reads the float32 A and stores it
+  // rounded to bfloat16; the other power-step passes read the copy (same bfloat16 values).
+  bool copy_ready = false;
   auto ax = [&](const double* Xs, bool last) -> hipError_t {
     if (!mixed) return gemm_ax_f64(A, a_dtype, lda, m, n, Xs, li, li, w.Y, li, s, TSSVD_PROF_AX);
-    const int kind = !last ? MIX_BF16 : (f32_final ? MIX_F32_AX : MIX_BF16X3);
+    const int kind = !last ? MIX_BF16P : (f32_final ? MIX_F32_AX : MIX_BF16X3);
     hipError_t e = pack_operand(Xs, n, li, li, kind, w.pack, s);
     if (e != hipSuccess) return e;
-    return gemm_ax_mixed(A32, lda, m, n, w.pack, li, w.Y, li, kind, s,
-                         last ? TSSVD_PROF_AX_FINAL : TSSVD_PROF_AX_BF16);
+    if (last)
+      return gemm_ax_mixed(A32, lda, m, n, w.pack, li, w.Y, li, kind, s, TSSVD_PROF_AX_FINAL);
+    if (copy_ready)
+      return gemm_ax_bf16c(w.Acopy, m, n, w.pack, li, w.Y, li, s, TSSVD_PROF_AX_BF16C);
+    copy_ready = w.Acopy != nullptr;
+    return gemm_ax_bf16p(A32, lda, m, n, w.pack, li, w.Y, li, w.Acopy, s, TSSVD_PROF_AX_BF16);
   };
   auto atq = [&](const double* Qs, bool last, double* Zout) -> hipError_t {
     if (!mixed)
@@ -463,6 +474,9 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
     const int kind = !last ? MIX_BF16 : (f32_final ? MIX_F32_ROWS : MIX_BF16X3);
     hipError_t e = pack_operand(Qs, m, li, li, kind, w.pack, s);
     if (e != hipSuccess) return e;
+    if (!last && copy_ready)
+      return gemm_atq_bf16c(w.Acopy, m, n, w.pack, li, Zout, li, w.part, s,
+                            TSSVD_PROF_ATQ_BF16C);
     return gemm_atq_mixed(A32, lda, m, n, w.pack, li, Zout, li, w.part, kind, s,
                           last ? TSSVD_PROF_ATQ_FINAL : TSSVD_PROF_ATQ_BF16);
   };

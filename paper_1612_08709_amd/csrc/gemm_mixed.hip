@@ -22,6 +22,13 @@
 
 namespace tsv {
 
+#ifndef AXF_RT
+#define AXF_RT 4
+#endif
+#ifndef AXC_RT
+#define AXC_RT 4
+#endif
+
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -46,6 +53,29 @@ __global__ void k_pack_bf16(const double* __restrict__ S, int64_t K, int l, int 
   const int64_t kb = t / NT;
   const int col = 16 * nt + (lane & 15);
   const int64_t k0 = 32 * kb + 8 * (lane >> 4);
+  bf16x8 v;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t k = k0 + e;
+    v[e] = (__bf16)((k < K && col < l) ? S[k * lds + col] : 0.0);
+  }
+  P[idx] = v;
+}
+
+// Paired layout for the first pass with the copy: in each 64-row group kg, lane (i, g)
+// of MFMA j in {0, 1} takes rows 64 kg + 16 g + 8 j + e, so a lane's A values for the two
+// MFMAs are 16 consecutive columns:
+//   P[((kg*2 + j)*NT + nt)*64 + lane][e] = S[64 kg + 16 (lane/16) + 8 j + e][16 nt + lane%16]
+__global__ void k_pack_bf16p(const double* __restrict__ S, int64_t K, int l, int lds, int NT,
+                             int64_t ng, bf16x8* __restrict__ P) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ng * 2 * NT * 64) return;
+  const int lane = (int)(idx & 63);
+  const int64_t t = idx >> 6;
+  const int nt = (int)(t % NT);
+  const int64_t kj = t / NT;  // kg * 2 + j
+  const int col = 16 * nt + (lane & 15);
+  const int64_t k0 = 64 * (kj >> 1) + 16 * (lane >> 4) + 8 * (kj & 1);
   bf16x8 v;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
@@ -558,6 +588,310 @@ __global__ __launch_bounds__(256) void k_atq_f32(const float* __restrict__ A, in
     }
 }
 
+// ---------------------------------------------------------------- bfloat16 copy of A
+// The power steps round A to bfloat16 in every pass.  The first pass can store the rounded
+// values once (row-major, leading dimension ldc = n rounded up to 64, zero-padded), and
+// the later power steps then stream that copy: half the bytes, bit-identical products.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Power-step Y = A X from the float32 A with the paired k layout (X packed as MIX_BF16P):
+// per 64-column group a lane reads 16 consecutive floats of each of its rows (four 16-byte
+// loads, 256 bytes per row across the four lane groups) and rounds them to bfloat16 for
+// two MFMAs.  With CW (first pass) it also stores those 32 bytes to the copy (128
+// contiguous bytes per row): long runs in both directions.
+template <int RT, int NT, bool VEC, bool CW>
+__global__ __launch_bounds__(256) void k_ax_bf16p(const float* __restrict__ A, int64_t lda,
+                                                  int64_t m, int n,
+                                                  const bf16x8* __restrict__ Xp, int l,
+                                                  double* __restrict__ Y, int ldy,
+                                                  bf16x8* __restrict__ Ac, int64_t ldc8) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t rbase = (int64_t)blockIdx.x * (64 * RT) + (int64_t)wave * (16 * RT);
+  f32x4 acc[RT][NT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const float* arow[RT];
+  bf16x8* crow[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int64_t row = rbase + 16 * rt + li;
+    arow[rt] = A + (row < m ? row : m - 1) * lda + 16 * g;
+    crow[rt] = (CW && row < m) ? Ac + row * ldc8 + 2 * g : nullptr;
+  }
+  const bf16x8* xp = Xp + lane;
+  auto load_a = [&](int kg, float (&v)[RT][16]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const float* p = arow[rt] + 64 * kg;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (VEC) {
+          const float4 x = *reinterpret_cast<const float4*>(p + 4 * q);
+          v[rt][4 * q] = x.x; v[rt][4 * q + 1] = x.y; v[rt][4 * q + 2] = x.z; v[rt][4 * q + 3] = x.w;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[rt][4 * q + e] = p[4 * q + e];
+        }
+      }
+    }
+  };
+  auto load_b = [&](int kg, bf16x8 (&b)[2][NT]) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) b[j][nt] = xp[((int64_t)(2 * kg + j) * NT + nt) * 64];
+  };
+  auto products = [&](const float (&v)[RT][16], const bf16x8 (&b)[2][NT], int kg) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      bf16x8 a[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[j][e] = (__bf16)v[rt][8 * j + e];
+      if (CW && crow[rt]) {
+        crow[rt][8 * kg] = a[0];
+        crow[rt][8 * kg + 1] = a[1];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mfma_bf16(a[j], b[j][nt], acc[rt][nt]);
+    }
+  };
+  const int nfull = n >> 6;
+  if (nfull > 0) {
+    float v0[RT][16], v1[RT][16];
+    bf16x8 b0[2][NT], b1[2][NT];
+    const int last = nfull - 1;
+    load_a(0, v0);
+    load_b(0, b0);
+    load_a(last < 1 ? last : 1, v1);
+    load_b(last < 1 ? last : 1, b1);
+    int kg = 0;
+    for (; kg + 2 <= nfull; kg += 2) {
+      products(v0, b0, kg);
+      __builtin_amdgcn_sched_barrier(0);
+      const int k2 = (kg + 2 < last) ? kg + 2 : last;
+      load_a(k2, v0);
+      load_b(k2, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      products(v1, b1, kg + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      const int k3 = (kg + 3 < last) ? kg + 3 : last;
+      load_a(k3, v1);
+      load_b(k3, b1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (kg < nfull) products(v0, b0, kg);
+  }
+  if ((nfull << 6) < n) {
+    // ragged last group: columns past n read as 0 (zero padding of the copy, zero X rows)
+    const int k0 = (nfull << 6) + 16 * g;
+    float v[RT][16];
+    bf16x8 b[2][NT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[rt][e] = (k0 + e < n) ? arow[rt][64 * nfull + e] : 0.f;
+    load_b(nfull, b);
+    products(v, b, nfull);
+  }
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int col = 16 * nt + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = rbase + 16 * rt + 4 * g + r;
+        if (row < m && col < l) Y[row * ldy + col] = (double)acc[rt][nt][r];
+      }
+    }
+}
+
+// Y = A X from the copy, paired k layout (X packed as MIX_BF16P): per 64-column group a
+// lane reads its 16 consecutive values of a row as two adjacent 16-byte fragments, used by
+// the two MFMAs as they are; same products in the same order as k_ax_bf16p, so the result
+// is bitwise that of rounding the float32 A in the pass.  Rows past m read row m-1.
+template <int RT, int NT>
+__global__ __launch_bounds__(256) void k_ax_bf16c(const bf16x8* __restrict__ Ac, int64_t ldc8,
+                                                  int64_t m, int ngroups,
+                                                  const bf16x8* __restrict__ Xp, int l,
+                                                  double* __restrict__ Y, int ldy) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t rbase = (int64_t)blockIdx.x * (64 * RT) + (int64_t)wave * (16 * RT);
+  f32x4 acc[RT][NT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16x8* arow[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int64_t row = rbase + 16 * rt + li;
+    arow[rt] = Ac + (row < m ? row : m - 1) * ldc8 + 2 * g;
+  }
+  const bf16x8* xp = Xp + lane;
+  auto load = [&](int kg, bf16x8 (&a)[2][RT], bf16x8 (&b)[2][NT]) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) a[j][rt] = arow[rt][8 * kg + j];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) b[j][nt] = xp[((int64_t)(2 * kg + j) * NT + nt) * 64];
+    }
+  };
+  auto products = [&](const bf16x8 (&a)[2][RT], const bf16x8 (&b)[2][NT]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mfma_bf16(a[j][rt], b[j][nt], acc[rt][nt]);
+  };
+  // two register sets, two groups in flight (as in k_ax_bf16)
+  bf16x8 a0[2][RT], a1[2][RT], b0[2][NT], b1[2][NT];
+  const int last = ngroups - 1;
+  load(0, a0, b0);
+  load(last < 1 ? last : 1, a1, b1);
+  int kg = 0;
+  for (; kg + 2 <= ngroups; kg += 2) {
+    products(a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    load((kg + 2 < last) ? kg + 2 : last, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    products(a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    load((kg + 3 < last) ? kg + 3 : last, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (kg < ngroups) products(a0, b0);
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int col = 16 * nt + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = rbase + 16 * rt + 4 * g + r;
+        if (row < m && col < l) Y[row * ldy + col] = (double)acc[rt][nt][r];
+      }
+    }
+}
+
+// Z = A^T Q from the copy: lane (i, g) reads 4 columns (8 bytes) of rows rb + 8g + t and
+// regroups them into the four MFMA fragments (tile e takes column cb + e), as k_atq_bf16.
+template <int NT>
+__device__ __forceinline__ void atqc_products(const uint2 (&v)[8], const bf16x8 (&b)[NT],
+                                              f32x4 (&acc)[4][NT]) {
+  bf16x8 a[4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    u32x4 lo, hi;  // tiles 2h (low halves) and 2h+1 (high halves), rows t in pairs
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const unsigned x0 = h ? v[2 * j].y : v[2 * j].x;
+      const unsigned x1 = h ? v[2 * j + 1].y : v[2 * j + 1].x;
+      lo[j] = (x0 & 0xFFFFu) | (x1 << 16);
+      hi[j] = (x0 >> 16) | (x1 & 0xFFFF0000u);
+    }
+    a[2 * h] = __builtin_bit_cast(bf16x8, lo);
+    a[2 * h + 1] = __builtin_bit_cast(bf16x8, hi);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[e][nt] = mfma_bf16(a[e], b[nt], acc[e][nt]);
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_atq_bf16c(const __bf16* __restrict__ Ac, int64_t ldc,
+                                                   int64_t m, int n,
+                                                   const bf16x8* __restrict__ Qp, int l,
+                                                   int ncol, int nchunk, int64_t chunk_rows,
+                                                   double* __restrict__ part) {
+  int chunk, ct;
+  bool ok;
+  mx_tile(ncol * nchunk, ncol, chunk, ct, ok);
+  if (!ok) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int cw = ct * MX_COLS + 64 * wave;
+  if (cw >= n) return;
+  const int64_t r0 = (int64_t)chunk * chunk_rows;  // chunk_rows is a multiple of 32
+  const int64_t r1 = (r0 + chunk_rows < m) ? r0 + chunk_rows : m;
+  const int cb = cw + 4 * li;
+  const bool cok = cb < ldc;  // ldc is a multiple of 32, so cb + 4 <= ldc
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[e][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16x8* qp = Qp + lane;
+  auto load = [&](int64_t rb, uint2 (&v)[8], bf16x8 (&b)[NT]) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const __bf16* p = Ac + (rb + 8 * g + t) * ldc + cb;
+      v[t] = cok ? *reinterpret_cast<const uint2*>(p) : make_uint2(0u, 0u);
+    }
+    const int64_t kb = rb >> 5;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) b[nt] = qp[(kb * NT + nt) * 64];
+  };
+  const int64_t rfull = r0 + (((r1 - r0) >> 5) << 5);
+  if (rfull > r0) {
+    uint2 v0[8], v1[8];
+    bf16x8 b0[NT], b1[NT];
+    const int64_t last = rfull - 32;
+    load(r0, v0, b0);
+    load((r0 + 32 < last) ? r0 + 32 : last, v1, b1);
+    int64_t rb = r0;
+    for (; rb + 64 <= rfull; rb += 64) {
+      atqc_products<NT>(v0, b0, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      load((rb + 64 < last) ? rb + 64 : last, v0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      atqc_products<NT>(v1, b1, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      load((rb + 96 < last) ? rb + 96 : last, v1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (rb < rfull) atqc_products<NT>(v0, b0, acc);
+  }
+  if (rfull < r1) {
+    // ragged last rows (only the chunk that ends at m): rows past r1 read as 0
+    uint2 v[8];
+    bf16x8 b[NT];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t row = rfull + 8 * g + t;
+      v[t] = (row < r1 && cok) ? *reinterpret_cast<const uint2*>(Ac + row * ldc + cb)
+                               : make_uint2(0u, 0u);
+    }
+    const int64_t kb = rfull >> 5;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) b[nt] = qp[(kb * NT + nt) * 64];
+    atqc_products<NT>(v, b, acc);
+  }
+  double* P = part + (int64_t)chunk * n * l;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int col = 16 * nt + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = cw + 4 * (4 * g + r) + e;
+        if (c < n && col < l) P[(int64_t)c * l + col] = (double)acc[e][nt][r];
+      }
+    }
+}
+
 // ---------------------------------------------------------------- host side
 static void mx_grid(int64_t m, int64_t n, int& ncol, int& nchunk, int64_t& chunk_rows) {
   ncol = (int)((n + MX_COLS - 1) / MX_COLS);
@@ -591,6 +925,11 @@ hipError_t pack_operand(const double* S, int64_t K, int l, int lds, int kind, vo
     const int64_t tot = nkb * NT * 64;
     hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, S, K,
                        l, lds, NT, nkb, (bf16x8*)P);
+  } else if (kind == MIX_BF16P) {
+    const int64_t ng = (K + 63) / 64;
+    const int64_t tot = ng * 2 * NT * 64;
+    hipLaunchKernelGGL(k_pack_bf16p, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, S,
+                       K, l, lds, NT, ng, (bf16x8*)P);
   } else if (kind == MIX_BF16X3) {
     const int64_t nkb = (K + 31) / 32;
     const int64_t tot = nkb * NT * 64;
@@ -707,6 +1046,109 @@ hipError_t gemm_atq_mixed(const float* A, int64_t lda, int64_t m, int64_t n, con
   int64_t cr;
   mx_grid(m, n, ncol, nchunk, cr);
   return reduce_chunks(part, nchunk, n, l, Z, ldz, s);
+}
+
+int64_t bf16_copy_ld(int64_t n) { return (n + 63) / 64 * 64; }
+
+size_t bf16_copy_bytes(int64_t m, int64_t n) { return (size_t)m * bf16_copy_ld(n) * 2; }
+
+template <int NT>
+static void launch_ax_bf16c(const void* Ac, int64_t m, int64_t n, const void* Xp, int l,
+                            double* Y, int ldy, hipStream_t s) {
+  constexpr int RT = AXC_RT;
+  const unsigned grid = (unsigned)((m + 64 * RT - 1) / (64 * RT));
+  const int64_t ldc = bf16_copy_ld(n);
+  hipLaunchKernelGGL((k_ax_bf16c<RT, NT>), dim3(grid), dim3(256), 0, s, (const bf16x8*)Ac,
+                     ldc / 8, m, (int)(ldc / 64), (const bf16x8*)Xp, l, Y, ldy);
+}
+
+hipError_t gemm_ax_bf16c(const void* Ac, int64_t m, int64_t n, const void* Xp, int l, double* Y,
+                         int ldy, hipStream_t s, int prof) {
+  prof_begin(prof, s);
+  switch ((l + 15) / 16) {
+    case 1: launch_ax_bf16c<1>(Ac, m, n, Xp, l, Y, ldy, s); break;
+    case 2: launch_ax_bf16c<2>(Ac, m, n, Xp, l, Y, ldy, s); break;
+    case 3: launch_ax_bf16c<3>(Ac, m, n, Xp, l, Y, ldy, s); break;
+    case 4: launch_ax_bf16c<4>(Ac, m, n, Xp, l, Y, ldy, s); break;
+    case 5: launch_ax_bf16c<5>(Ac, m, n, Xp, l, Y, ldy, s); break;
+    case 6: launch_ax_bf16c<6>(Ac, m, n, Xp, l, Y, ldy, s); break;
+    case 7: launch_ax_bf16c<7>(Ac, m, n, Xp, l, Y, ldy, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  prof_end(prof, s);
+  return hipGetLastError();
+}
+
+template <int NT>
+static void launch_atq_bf16c(const void* Ac, int64_t m, int64_t n, const void* Qp, int l,
+                             double* part, hipStream_t s) {
+  int ncol, nchunk;
+  int64_t cr;
+  mx_grid(m, n, ncol, nchunk, cr);
+  const int total = ncol * nchunk;
+  const int grid = ((total + 7) / 8) * 8;
+  hipLaunchKernelGGL((k_atq_bf16c<NT>), dim3(grid), dim3(256), 0, s, (const __bf16*)Ac,
+                     bf16_copy_ld(n), m, (int)n, (const bf16x8*)Qp, l, ncol, nchunk, cr, part);
+}
+
+hipError_t gemm_atq_bf16c(const void* Ac, int64_t m, int64_t n, const void* Qp, int l,
+                          double* Z, int ldz, double* part, hipStream_t s, int prof) {
+  prof_begin(prof, s);
+  switch ((l + 15) / 16) {
+    case 1: launch_atq_bf16c<1>(Ac, m, n, Qp, l, part, s); break;
+    case 2: launch_atq_bf16c<2>(Ac, m, n, Qp, l, part, s); break;
+    case 3: launch_atq_bf16c<3>(Ac, m, n, Qp, l, part, s); break;
+    case 4: launch_atq_bf16c<4>(Ac, m, n, Qp, l, part, s); break;
+    case 5: launch_atq_bf16c<5>(Ac, m, n, Qp, l, part, s); break;
+    case 6: launch_atq_bf16c<6>(Ac, m, n, Qp, l, part, s); break;
+    case 7: launch_atq_bf16c<7>(Ac, m, n, Qp, l, part, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  prof_end(prof, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int ncol, nchunk;
+  int64_t cr;
+  mx_grid(m, n, ncol, nchunk, cr);
+  return reduce_chunks(part, nchunk, n, l, Z, ldz, s);
+}
+
+template <int NT>
+static void launch_ax_bf16p(const float* A, int64_t lda, int64_t m, int64_t n, const void* Xp,
+                            int l, double* Y, int ldy, void* Ac, hipStream_t s) {
+  constexpr int RT = AXF_RT;
+  const unsigned grid = (unsigned)((m + 64 * RT - 1) / (64 * RT));
+  const bool vec = (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda & 3) == 0;
+  const int64_t ldc8 = bf16_copy_ld(n) / 8;
+  if (vec && Ac)
+    hipLaunchKernelGGL((k_ax_bf16p<RT, NT, true, true>), dim3(grid), dim3(256), 0, s, A, lda,
+                       m, (int)n, (const bf16x8*)Xp, l, Y, ldy, (bf16x8*)Ac, ldc8);
+  else if (Ac)
+    hipLaunchKernelGGL((k_ax_bf16p<RT, NT, false, true>), dim3(grid), dim3(256), 0, s, A, lda,
+                       m, (int)n, (const bf16x8*)Xp, l, Y, ldy, (bf16x8*)Ac, ldc8);
+  else if (vec)
+    hipLaunchKernelGGL((k_ax_bf16p<RT, NT, true, false>), dim3(grid), dim3(256), 0, s, A, lda,
+                       m, (int)n, (const bf16x8*)Xp, l, Y, ldy, nullptr, ldc8);
+  else
+    hipLaunchKernelGGL((k_ax_bf16p<RT, NT, false, false>), dim3(grid), dim3(256), 0, s, A, lda,
+                       m, (int)n, (const bf16x8*)Xp, l, Y, ldy, nullptr, ldc8);
+}
+
+hipError_t gemm_ax_bf16p(const float* A, int64_t lda, int64_t m, int64_t n, const void* Xp,
+                         int l, double* Y, int ldy, void* Acopy, hipStream_t s, int prof) {
+  prof_begin(prof, s);
+  switch ((l + 15) / 16) {
+    case 1: launch_ax_bf16p<1>(A, lda, m, n, Xp, l, Y, ldy, Acopy, s); break;
+    case 2: launch_ax_bf16p<2>(A, lda, m, n, Xp, l, Y, ldy, Acopy, s); break;
+    case 3: launch_ax_bf16p<3>(A, lda, m, n, Xp, l, Y, ldy, Acopy, s); break;
+    case 4: launch_ax_bf16p<4>(A, lda, m, n, Xp, l, Y, ldy, Acopy, s); break;
+    case 5: launch_ax_bf16p<5>(A, lda, m, n, Xp, l, Y, ldy, Acopy, s); break;
+    case 6: launch_ax_bf16p<6>(A, lda, m, n, Xp, l, Y, ldy, Acopy, s); break;
+    case 7: launch_ax_bf16p<7>(A, lda, m, n, Xp, l, Y, ldy, Acopy, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  prof_end(prof, s);
+  return hipGetLastError();
 }
 
 }  // namespace tsv

@@ -90,6 +90,7 @@ constexpr int MIX_BF16 = 0;    // bfloat16 inputs, float32 accumulation
 constexpr int MIX_F32_AX = 1;  // float32 inputs, packed for Y = A X
 constexpr int MIX_F32_ROWS = 2;  // float32 inputs, padded rows for Z = A^T Q
 constexpr int MIX_BF16X3 = 3;  // float32-accurate inputs as three exact bfloat16 pieces
+constexpr int MIX_BF16P = 4;   // bfloat16, k paired in 64-column groups (first pass with copy)
 size_t mixed_partials(int64_t m, int64_t n, int l);
 size_t mixed_pack_bytes(int64_t K, int l);
 // Pack the K x l float64 operand S (stride lds) for the kernels below.
@@ -98,6 +99,18 @@ hipError_t pack_operand(const double* S, int64_t K, int l, int lds, int kind, vo
 // Y (m x l) = A X with X packed as MIX_BF16 or MIX_F32_AX.
 hipError_t gemm_ax_mixed(const float* A, int64_t lda, int64_t m, int64_t n, const void* Xp,
                          int l, double* Y, int ldy, int kind, hipStream_t s, int prof = -1);
+// Power-step Y = A X from the float32 A, bfloat16 inputs, X packed as MIX_BF16P; with
+// Acopy non-null it also stores the bfloat16 copy of A (first pass).
+hipError_t gemm_ax_bf16p(const float* A, int64_t lda, int64_t m, int64_t n, const void* Xp,
+                         int l, double* Y, int ldy, void* Acopy, hipStream_t s, int prof = -1);
+// bfloat16 copy of A: row-major m x bf16_copy_ld(n) (n rounded up to 64, zero-padded).
+int64_t bf16_copy_ld(int64_t n);
+size_t bf16_copy_bytes(int64_t m, int64_t n);
+// Y = A X (X packed as MIX_BF16P) and Z = A^T Q (Q packed as MIX_BF16) reading the copy.
+hipError_t gemm_ax_bf16c(const void* Ac, int64_t m, int64_t n, const void* Xp, int l, double* Y,
+                         int ldy, hipStream_t s, int prof = -1);
+hipError_t gemm_atq_bf16c(const void* Ac, int64_t m, int64_t n, const void* Qp, int l,
+                          double* Z, int ldz, double* part, hipStream_t s, int prof = -1);
 // Z (n x l) = A^T Q with Q packed as MIX_BF16 or MIX_F32_ROWS (kind MIX_F32_ROWS selects
 // the float32 kernel).
 hipError_t gemm_atq_mixed(const float* A, int64_t lda, int64_t m, int64_t n, const void* Qp,

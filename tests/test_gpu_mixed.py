@@ -79,6 +79,18 @@ def test_mixed_deterministic_bitwise():
         assert np.array_equal(a, b)
 
 
+def test_bf16_copy_of_a_is_bitwise_neutral():
+    """The power steps reading the bfloat16 copy of A give bit-identical results to
+    rounding the float32 A in every pass (TSSVD_FLAG_NO_A_COPY); odd n and ragged m."""
+    A32, _ = _workload4_like(9001, 777, 78, r=250)
+    Om = dev(sm.sketch(777, 36, 78))
+    Ad = dev(A32)
+    a = [host(x) for x in T.lowrank_svd(Ad, 24, 36, 3, Om, prec=T.PREC_MIXED)[:3]]
+    b = [host(x) for x in T.lowrank_svd(Ad, 24, 36, 3, Om, prec=T.PREC_MIXED, flags=2)[:3]]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
 def test_f32_mfma_final_flag_same_result_class():
     """The float32-MFMA final products (flag) and the default exact bf16 split agree."""
     A32, _ = _workload4_like(12000, 900, 77, r=300)
