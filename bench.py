@@ -148,7 +148,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "paper_1612_08709_amd", "csrc")
 TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "hbm_traffic_workload4.md")
 KERNEL_SYMBOLS = {  # profile marker name -> (regex on the kernel symbol, source files)
-    "ax_bf16": (r"k_ax_bf16<\d+, \d+, 1[,>]", ["gemm_mixed.hip"]),
+    "ax_bf16": (r"k_ax_bf16p<", ["gemm_mixed.hip"]),
     "atq_bf16": (r"k_atq_bf16<\d+, 1[,>]", ["gemm_mixed.hip"]),
     "ax_bf16c": (r"k_ax_bf16c<", ["gemm_mixed.hip"]),
     "atq_bf16c": (r"k_atq_bf16c<", ["gemm_mixed.hip"]),
