@@ -246,14 +246,15 @@ def summarize_trace(d, command):
         rows = list(csv.DictReader(fh))
     lines = ["# Kernel trace: " + os.path.basename(os.path.normpath(d)), "",
              "Command (from the repository root):", "", "```", command, "```", "",
-             "Library kernels (namespace `tsv`), all calls in the run (warm-up, timed and "
+             "Library kernels, all calls in the run (warm-up, timed and "
              "checking calls):", "",
              "| kernel | calls | total ms | average us | min us | max us |",
              "|---|---|---|---|---|---|"]
     other_ms, other_calls = 0.0, 0
     for r in rows:
-        name = r["Name"].split("(")[0]
-        if "tsv::" not in name:
+        name = r["Name"]
+        name = name[:name.index("(", 1)] if name.startswith("(anonymous") else name.split("(")[0]
+        if "tsv::" not in name and not name.startswith("(anonymous namespace)::k_"):
             other_ms += float(r["TotalDurationNs"]) / 1e6
             other_calls += int(r["Calls"])
             continue

@@ -71,80 +71,109 @@ __global__ void k_ortho_gate(const double* __restrict__ G, int k, int mode, doub
   }
 }
 
+// R with R^T R = G (Cholesky, R upper triangular, row-major l x l) for the Gram G = Y^T Y of
+// an intermediate basis.  One workgroup, G in LDS, right-looking with one barrier per step:
+// step k writes row k of R (G_kj / sqrt(G_kk)) and updates the trailing upper triangle,
+// G_ij -= G_ki G_kj / G_kk, on a 16 x 16 thread grid.  *bad = 1 when a pivot is not
+// positive and finite (then R is left unspecified).
+__global__ __launch_bounds__(256) void k_chol(const double* __restrict__ G, int l,
+                                              double* __restrict__ R, int* __restrict__ bad) {
+  extern __shared__ double Gs[];  // l x l, row-major
+  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  for (int i = tid; i < l * l; i += 256) {
+    Gs[i] = G[i];
+    R[i] = 0.0;
+  }
+  __syncthreads();
+  int fail = 0;
+  for (int k = 0; k < l; ++k) {
+    const double piv = Gs[k * l + k];
+    if (!(piv > 0.0) || !isfinite(piv)) {  // uniform: every thread reads the same pivot
+      fail = 1;
+      break;
+    }
+    const double rd = 1.0 / sqrt(piv), inv = 1.0 / piv;
+    for (int j = k + tid; j < l; j += 256) R[k * l + j] = Gs[k * l + j] * rd;
+    for (int i = k + 1 + ti; i < l; i += 16) {
+      const double gki = Gs[k * l + i] * inv;
+      for (int j = k + 1 + tj; j < l; j += 16)
+        if (j >= i) Gs[i * l + j] = fma(-gki, Gs[k * l + j], Gs[i * l + j]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *bad = fail;
+}
+
 // Intermediate bases of the subspace iteration (Algorithm 5 before its last step) enter
 // only through products with A, and Q = Y R^-1 spans the same space as the TSQR's
 // Householder Q (the paper's own TSQR formed Q = A R^-1).  With T = R^-1 the m x l basis
 // need not be formed by the reverse Householder pass.  Rounding in Y R^-1 grows with
 // kappa(R); when the Frobenius estimate ||R||_F ||R^-1||_F exceeds kappa_max (or R^-1 is
 // not finite, e.g. for a rank-deficient sketch) the kernel sets *use_q = 1 and T = I, and
-// the gated Householder apply forms Q explicitly.  One workgroup computes T row by row
-// from the bottom (back substitution for all columns at once; R and T packed in LDS).
-__device__ __forceinline__ int upper_idx(int i, int c, int l) {
-  return i * l - ((i * (i - 1)) >> 1) + (c - i);  // packed upper triangle, row-major
-}
+// the gated Householder apply forms Q explicitly.
+// 1024 threads: the 16-lane group c (c += 64) solves R t = e_c bottom-up with no barrier;
+// lane L keeps t_k for k = L (mod 16) in registers and the dot products are 16-lane sums.
+constexpr int RINV_THREADS = 1024;
+constexpr int RINV_SLOTS = (TSSVD_N_MAX + 15) / 16;
 
-__global__ __launch_bounds__(256) void k_rinv_gate(const double* __restrict__ R, int l,
-                                                   double kappa_max, double* __restrict__ T,
-                                                   int* __restrict__ use_q) {
-  extern __shared__ double sm[];  // packed upper triangles: R, then T = R^-1
-  const int np = l * (l + 1) / 2;
-  double* Rs = sm;
-  double* Ts = sm + np;
-  __shared__ double red[2][256];
+__global__ __launch_bounds__(RINV_THREADS) void k_rinv_gate(const double* __restrict__ R, int l,
+                                                            double kappa_max,
+                                                            double* __restrict__ T,
+                                                            int* __restrict__ use_q,
+                                                            const int* __restrict__ force) {
+  extern __shared__ double Rs[];  // l x l, row-major
+  __shared__ double red[2][RINV_THREADS / 16];
   __shared__ int bad;
-  const int tid = threadIdx.x;
-  double rn = 0.0;
-  for (int idx = tid; idx < l * l; idx += 256) {
-    const int i = idx / l, c = idx - i * l;
-    if (c >= i) {
-      const double r = R[idx];
-      Rs[upper_idx(i, c, l)] = r;
-      rn = fma(r, r, rn);
-    }
-  }
+  const int tid = threadIdx.x, L = tid & 15, grp = tid >> 4;
+  for (int i = tid; i < l * l; i += RINV_THREADS) Rs[i] = R[i];
   __syncthreads();
-  // rows of T bottom-up: T[i][c] = (delta_ic - sum_{i<k<=c} R[i][k] T[k][c]) / R[i][i].
-  // Each column's sum is split over the four lanes of a quad (k = i+1+q, +4, ...) and
-  // combined with a quad reduction.
-  const int q4 = tid & 3, cq = tid >> 2;
-  for (int i = l - 1; i >= 0; --i) {
-    const double* ri = Rs + upper_idx(i, i, l) - i;  // ri[k] = R[i][k], k >= i
-    for (int c0 = 0; c0 < l; c0 += 64) {
-      const int c = c0 + cq;
-      const bool live = c < l && c >= i;
-      double acc = 0.0;
-      if (live) {
-#pragma unroll 4
-        for (int k2 = i + 1 + q4; k2 <= c; k2 += 4)
-          acc = fma(-ri[k2], Ts[upper_idx(k2, c, l)], acc);
-      }
-      acc = sum4(acc);
-      if (live && q4 == 0) Ts[upper_idx(i, c, l)] = ((c == i ? 1.0 : 0.0) + acc) / ri[i];
-    }
-    __syncthreads();
-  }
   double tn = 0.0;
-  for (int idx = tid; idx < np; idx += 256) tn = fma(Ts[idx], Ts[idx], tn);
-  red[0][tid] = tn;
-  red[1][tid] = rn;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) {
-      red[0][tid] += red[0][tid + w];
-      red[1][tid] += red[1][tid + w];
+  for (int c = grp; c < l; c += RINV_THREADS / 16) {
+    double tk[RINV_SLOTS];
+#pragma unroll
+    for (int q = 0; q < RINV_SLOTS; ++q) tk[q] = 0.0;
+    for (int i = c; i >= 0; --i) {
+      double part = 0.0;
+#pragma unroll
+      for (int q = 0; q < RINV_SLOTS; ++q) {
+        const int k = 16 * q + L;
+        if (k > i && k <= c) part = fma(Rs[i * l + k], tk[q], part);
+      }
+      const double ti = ((i == c ? 1.0 : 0.0) - sum16(part)) / Rs[i * l + i];
+#pragma unroll
+      for (int q = 0; q < RINV_SLOTS; ++q)
+        if (16 * q + L == i) tk[q] = ti;
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RINV_SLOTS; ++q) {
+      const int k = 16 * q + L;
+      if (k < l) T[k * l + c] = (k <= c) ? tk[q] : 0.0;
+      tn = fma(tk[q], tk[q], tn);
+    }
   }
+  double rn = 0.0;
+  for (int idx = tid; idx < l * l; idx += RINV_THREADS) rn = fma(Rs[idx], Rs[idx], rn);
+  tn = sum16(tn);
+  rn = sum16(rn);
+  if (L == 0) {
+    red[0][grp] = tn;
+    red[1][grp] = rn;
+  }
+  __syncthreads();
   if (tid == 0) {
-    const double kap = sqrt(red[0][0]) * sqrt(red[1][0]);
-    bad = !(kap <= kappa_max);  // also catches NaN / Inf
+    double a = 0.0, b = 0.0;
+    for (int g2 = 0; g2 < RINV_THREADS / 16; ++g2) {
+      a += red[0][g2];
+      b += red[1][g2];
+    }
+    const double kap = sqrt(a) * sqrt(b);
+    bad = !(kap <= kappa_max) || (force && *force);  // also catches NaN / Inf
     *use_q = bad;
   }
   __syncthreads();
-  for (int idx = tid; idx < l * l; idx += 256) {
-    const int i = idx / l, c = idx - i * l;
-    T[idx] = bad ? (i == c ? 1.0 : 0.0) : (c >= i ? Ts[upper_idx(i, c, l)] : 0.0);
-  }
+  if (bad)
+    for (int idx = tid; idx < l * l; idx += RINV_THREADS)
+      T[idx] = (idx / l == idx % l) ? 1.0 : 0.0;
 }
 
 // T = R diag(S) (n x n), for the second orthonormalization of U = Q2 R2.
@@ -325,7 +354,7 @@ namespace {
 
 struct LowrankWs {
   TsqrPlan pY, pZ;
-  double *X, *Y, *Z, *Zraw, *Qy, *part, *I, *P, *sig, *W, *Wk, *G, *ortho, *Tq;
+  double *X, *Y, *Z, *Zraw, *Qy, *part, *I, *P, *sig, *W, *Wk, *G, *ortho, *Tq, *Rc;
   void* pack;
   void* Acopy;  // bfloat16 copy of A for the mixed power steps (or null)
   int* gate;
@@ -347,6 +376,8 @@ LowrankWs lowrank_layout(int64_t m, int64_t n, int k, int l, void* work, bool mi
   size_t np = atq_partials(m, n, l);
   const size_t np2 = atq_partials(m, l, l);
   if (np2 > np) np = np2;
+  const size_t np3 = atq_partials(n, l, l);
+  if (np3 > np) np = np3;
   if (mixed && mixed_partials(m, n, l) > np) np = mixed_partials(m, n, l);
   w.part = c.take<double>(np);
   w.pack = nullptr;
@@ -366,6 +397,7 @@ LowrankWs lowrank_layout(int64_t m, int64_t n, int k, int l, void* work, bool mi
   w.Wk = c.take<double>((size_t)l * k);
   w.G = c.take<double>(ll);
   w.Tq = c.take<double>(ll);
+  w.Rc = c.take<double>(ll);
   w.ortho = c.take<double>(1);
   w.gate = c.take<int>(4);
   w.bytes = c.off + 256;
@@ -381,25 +413,37 @@ int lowrank_check(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t 
 }
 
 // Orthonormal basis of span(Y) by TSQR, written over Y (m x l).
-// Basis of an intermediate step: factor Y, then either T = R^-1 (Y kept) or, when R is too
-// ill-conditioned, the explicit Householder Q written over Y and T = I (device-side choice).
-constexpr double kKappaMax = 1e6;
-hipError_t basis_via_r(const TsqrPlan& p, double* Y, int l, const double* I, double* T,
-                       int* use_q, hipStream_t s) {
-  hipError_t e = tsqr_factor(p, Y, TSSVD_F64, l, s);
+// Basis of an intermediate step (rows x l, row-major): R from the Cholesky factor of the
+// Gram Y^T Y (CholeskyQR), T = R^-1, Y kept.  The basis Y R^-1 loses orthogonality like
+// kappa(Y)^2 eps, harmless for an intermediate step as long as kappa is moderate, so when
+// the Cholesky factorization fails or ||R||_F ||R^-1||_F > 1e4 the device gate falls back to
+// the TSQR of Y with the explicit Householder Q written over Y and T = I.
+constexpr double kKappaMax = 1e4;
+hipError_t basis_via_r(const TsqrPlan& p, double* Y, int64_t rows, int l, const double* I,
+                       double* T, double* G, double* Rc, double* part, int* flags,
+                       hipStream_t s) {
+  int* use_q = flags;
+  int* chol_bad = flags + 1;
+  hipError_t e = gemm_atq_f64(Y, TSSVD_F64, l, rows, l, Y, l, l, G, l, part, s);  // Y^T Y
   if (e != hipSuccess) return e;
-  const size_t lds = (size_t)l * (l + 1) * sizeof(double);
   static bool attr_set = false;  // the attribute is per function; setting it twice is harmless
   if (!attr_set) {
     e = hipFuncSetAttribute((const void*)k_rinv_gate,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024 - 8192);
+    if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(256), lds, s, tsqr_root(p), l, kKappaMax, T,
-                     use_q);
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), (size_t)l * l * sizeof(double), s, G, l, Rc,
+                     chol_bad);
+  hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), (size_t)l * l * sizeof(double),
+                     s, Rc, l, kKappaMax, T, use_q, chol_bad);
   TsqrPlan pq = p;
   pq.gate = use_q;
+  e = tsqr_factor(pq, Y, TSSVD_F64, l, s);
+  if (e != hipSuccess) return e;
   return tsqr_apply(pq, I, l, Y, l, s);
 }
 
@@ -487,7 +531,7 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   int* use_q = w.gate + 1;
   TRY(ax(w.X, q == 0));                                                        // A Q~_0
   for (int64_t j = 0; j < q; ++j) {
-    TRY(basis_via_r(w.pY, w.Y, li, w.I, w.Tq, use_q, s));                      // Q_j = Y T
+    TRY(basis_via_r(w.pY, w.Y, m, li, w.I, w.Tq, w.G, w.Rc, w.part, use_q, s));  // Q_j = Y T
     if (mixed) {
       TRY(gemm_ax_f64(w.Y, TSSVD_F64, l, m, l, w.Tq, li, li, w.Qy, li, s));   // Q_j
       TRY(atq(w.Qy, false, w.Z));                                              // A^* Q_j
@@ -495,7 +539,7 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
       TRY(atq(w.Y, false, w.Zraw));                                            // A^* Y
       TRY(gemm_ax_f64(w.Zraw, TSSVD_F64, l, n, l, w.Tq, li, li, w.Z, li, s)); // A^* Q_j
     }
-    TRY(basis_via_r(w.pZ, w.Z, li, w.I, w.Tq, use_q, s));                      // Q~_j = Z T
+    TRY(basis_via_r(w.pZ, w.Z, n, li, w.I, w.Tq, w.G, w.Rc, w.part, use_q, s));  // Q~_j = Z T
     TRY(gemm_ax_f64(w.Z, TSSVD_F64, l, n, l, w.Tq, li, li, w.X, li, s));
     TRY(ax(w.X, j == q - 1));                                                  // A Q~_j
   }

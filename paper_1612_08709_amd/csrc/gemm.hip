@@ -175,21 +175,25 @@ hipError_t gemm_ax_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int64
 // The contraction runs over rows: in one MFMA, k-slot g is row r + g.
 constexpr int ATQ_COLS = 256;
 
-template <int NT, typename TA>
+template <int NT, typename TA, bool RS>
 __global__ __launch_bounds__(256) void k_gemm_atq_f64(const TA* __restrict__ A, int64_t lda,
                                                       int64_t m, int n,
                                                       const double* __restrict__ Q, int ldq,
                                                       int l, int ncol, int nchunk,
                                                       int64_t chunk_rows,
                                                       double* __restrict__ part) {
-  const int total = ncol * nchunk;
+  // RS (n <= 64, one column tile of one wave): every wave takes a row chunk of its own
+  constexpr bool rowsplit = RS;
+  const int total = rowsplit ? (nchunk + 3) / 4 : ncol * nchunk;
   const int per = (total + 7) / 8;
   const int L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (L >= total) return;
-  const int chunk = L / ncol, ct = L - chunk * ncol;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int chunk = rowsplit ? 4 * L + wave : L / ncol;
+  const int ct = rowsplit ? 0 : L - chunk * ncol;
+  if (chunk >= nchunk) return;
   const int li = lane & 15, g = lane >> 4;
-  const int cw = ct * ATQ_COLS + 64 * wave;
+  const int cw = rowsplit ? 0 : ct * ATQ_COLS + 64 * wave;
   if (cw >= n) return;
   const int64_t r0 = (int64_t)chunk * chunk_rows;
   const int64_t r1 = (r0 + chunk_rows < m) ? r0 + chunk_rows : m;
@@ -245,6 +249,18 @@ __global__ __launch_bounds__(256) void k_gemm_atq_f64(const TA* __restrict__ A, 
     }
 }
 
+__global__ void k_reduce_chunks_strided(const double* __restrict__ part, int nchunk,
+                                        int64_t count, int64_t stride, double* __restrict__ Z,
+                                        int l, int ldz) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * stride + idx];
+  const int64_t row = idx / l;
+  const int col = (int)(idx - row * l);
+  Z[row * ldz + col] = s;
+}
+
 __global__ void k_reduce_chunks(const double* __restrict__ part, int nchunk, int64_t count,
                                 double* __restrict__ Z, int l, int ldz) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -268,8 +284,9 @@ __global__ void k_reduce_chunks(const double* __restrict__ part, int nchunk, int
 
 static void atq_grid(int64_t m, int64_t n, int& ncol, int& nchunk, int64_t& chunk_rows) {
   ncol = (int)((n + ATQ_COLS - 1) / ATQ_COLS);
-  int64_t want = (1024 + ncol - 1) / ncol;
-  const int64_t maxc = (m + 255) / 256;
+  // n <= 64: one wave per row chunk (see the kernel), so ask for four chunks per workgroup
+  int64_t want = n <= 64 ? 4096 : (1024 + ncol - 1) / ncol;
+  const int64_t maxc = n <= 64 ? (m + 63) / 64 : (m + 255) / 256;
   if (want > maxc) want = maxc;
   if (want < 1) want = 1;
   chunk_rows = (m + want - 1) / want;
@@ -290,10 +307,14 @@ static void launch_atq(const TA* A, int64_t lda, int64_t m, int64_t n, const dou
   int ncol, nchunk;
   int64_t cr;
   atq_grid(m, n, ncol, nchunk, cr);
-  const int total = ncol * nchunk;
+  const int total = n <= 64 ? (nchunk + 3) / 4 : ncol * nchunk;
   const int grid = ((total + 7) / 8) * 8;
-  hipLaunchKernelGGL((k_gemm_atq_f64<NT, TA>), dim3(grid), dim3(256), 0, s, A, lda, m, (int)n,
-                     Q, ldq, l, ncol, nchunk, cr, part);
+  if (n <= 64)
+    hipLaunchKernelGGL((k_gemm_atq_f64<NT, TA, true>), dim3(grid), dim3(256), 0, s, A, lda, m,
+                       (int)n, Q, ldq, l, ncol, nchunk, cr, part);
+  else
+    hipLaunchKernelGGL((k_gemm_atq_f64<NT, TA, false>), dim3(grid), dim3(256), 0, s, A, lda, m,
+                       (int)n, Q, ldq, l, ncol, nchunk, cr, part);
 }
 
 template <typename TA>
@@ -327,9 +348,40 @@ hipError_t gemm_atq_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int6
   return reduce_chunks(part, nchunk, n, l, Z, ldz, s);
 }
 
+// First level for many chunks: group gi adds chunks gi*G .. gi*G + G - 1 (in order) and
+// stores the sum over chunk gi*G's slot, which only this group reads.
+__global__ void k_reduce_groups(double* __restrict__ part, int nchunk, int64_t count, int G) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  const int c0 = blockIdx.y * G;
+  const int c1 = (c0 + G < nchunk) ? c0 + G : nchunk;
+  double s = 0.0;
+  int c = c0;
+  for (; c + 8 <= c1; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = part[(int64_t)(c + j) * count + idx];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += v[j];
+  }
+  for (; c < c1; ++c) s += part[(int64_t)c * count + idx];
+  part[(int64_t)c0 * count + idx] = s;
+}
+
 hipError_t reduce_chunks(const double* part, int nchunk, int64_t n, int l, double* Z, int ldz,
                          hipStream_t s) {
   const int64_t count = n * (int64_t)l;
+  if (nchunk > 64 && count < (1 << 16)) {
+    // few outputs, many chunks (Grams of tall matrices): two fixed-order levels, so the
+    // sums run on many threads instead of one long chain per output
+    const int G = (nchunk + 63) / 64;
+    const int ng = (nchunk + G - 1) / G;
+    hipLaunchKernelGGL(k_reduce_groups, dim3((unsigned)((count + 255) / 256), ng), dim3(256), 0,
+                       s, const_cast<double*>(part), nchunk, count, G);
+    hipLaunchKernelGGL(k_reduce_chunks_strided, dim3((unsigned)((count + 255) / 256)),
+                       dim3(256), 0, s, part, ng, count, (int64_t)G * count, Z, l, ldz);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
                      part, nchunk, count, Z, l, ldz);
   return hipGetLastError();
