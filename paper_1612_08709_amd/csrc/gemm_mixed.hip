@@ -113,13 +113,28 @@ __global__ void k_pack_f32_rows(const double* __restrict__ S, int64_t K, int l, 
   P[idx] = (r < K && c < l) ? (float)S[r * lds + c] : 0.0f;
 }
 
-// Exact three-way bfloat16 split of a float32 value: a = a1 + a2 + a3 (each a1, a2, a3 is
-// the nearest bfloat16 of what is left; a float32 significand has 24 bits = 3 x 8).
-__device__ __forceinline__ void split3(float a, __bf16& a1, __bf16& a2, __bf16& a3) {
-  a1 = (__bf16)a;
-  const float r1 = a - (float)a1;
-  a2 = (__bf16)r1;
-  a3 = (__bf16)(r1 - (float)a2);
+// Exact three-way bfloat16 split of float32 values, a pair at a time: x = x1 + x2 + x3,
+// each piece the nearest bfloat16 of what is left (a float32 significand has 24 bits =
+// 3 x 8).  The pieces come as packed bfloat16 pairs (low half = x0): one packed
+// round-to-nearest-even conversion per piece and pair; a piece is widened back to float32
+// with a shift (low half) or a mask (high half), both exact.
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ unsigned cvt_pk_bf16(float x0, float x1) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2v{x0, x1}, bf16x2v));
+}
+__device__ __forceinline__ float bf16_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+
+template <int PIECES>
+__device__ __forceinline__ void split_pk(float x0, float x1, unsigned (&w)[PIECES]) {
+  w[0] = cvt_pk_bf16(x0, x1);
+  if (PIECES == 3) {
+    const float r0 = x0 - bf16_lo(w[0]), r1 = x1 - bf16_hi(w[0]);
+    w[1 % PIECES] = cvt_pk_bf16(r0, r1);
+    w[2 % PIECES] = cvt_pk_bf16(r0 - bf16_lo(w[1 % PIECES]), r1 - bf16_hi(w[1 % PIECES]));
+  }
 }
 
 // Three bfloat16 pieces of the float64 operand, each the nearest bfloat16 of what is left
@@ -168,42 +183,55 @@ __device__ __forceinline__ bool aligned16(const void* p) {
 // steps with no bounds tests (rows past m read row m-1 and are not stored); a ragged last
 // step reads with tests.  The A and X fragments of step kb+1 are loaded before the
 // products of step kb.
-template <int PIECES>
-__device__ __forceinline__ void to_pieces(float x, __bf16 (&p)[3]) {
-  if (PIECES == 1) {
-    p[0] = (__bf16)x;
+//
+// The products, smallest first into every accumulator (the same order per accumulator
+// either way); PMAJOR (product-major) keeps consecutive matrix-core instructions
+// independent, which suits Y = A X, while A^T Q runs faster tile-major.
+template <int R, int NT, int PIECES, bool PMAJOR>
+__device__ __forceinline__ void mfma_pieces(const bf16x8 (&a)[PIECES][R],
+                                            const bf16x8 (&b)[PIECES][NT],
+                                            f32x4 (&acc)[R][NT]) {
+  constexpr int np = PIECES == 3 ? 6 : 1;
+  // product q: piece pa(q) of A times piece pb(q) of the other operand
+  auto pa = [](int q) { return (q == 0 ? 2 : q == 2 || q == 3 ? 1 : 0) % PIECES; };
+  auto pb = [](int q) { return (q == 1 ? 2 : q == 2 || q == 4 ? 1 : 0) % PIECES; };
+  if (PMAJOR) {
+#pragma unroll
+    for (int q = 6 - np; q < 6; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[r][nt] = mfma_bf16(a[pa(q)][r], b[pb(q)][nt], acc[r][nt]);
   } else {
-    split3(x, p[0], p[1], p[2]);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int q = 6 - np; q < 6; ++q)
+          acc[r][nt] = mfma_bf16(a[pa(q)][r], b[pb(q)][nt], acc[r][nt]);
   }
 }
 
-template <int RT, int NT, int PIECES>
-__device__ __forceinline__ void ax_products(const float (&v)[RT][8],
-                                            const bf16x8 (&b)[PIECES][NT],
-                                            f32x4 (&acc)[RT][NT]) {
-  bf16x8 a[PIECES][RT];
+template <int R, int PIECES>
+__device__ __forceinline__ void to_pieces_rows(const float (&v)[R][8], bf16x8 (&a)[PIECES][R]) {
+  if (PIECES == 1) {
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      __bf16 p[3];
-      to_pieces<PIECES>(v[rt][e], p);
+      for (int e = 0; e < 8; ++e) a[0][r][e] = (__bf16)v[r][e];
+    return;
+  }
 #pragma unroll
-      for (int pc = 0; pc < PIECES; ++pc) a[pc][rt][e] = p[pc];
-    }
+  for (int r = 0; r < R; ++r) {
+    unsigned w[4][PIECES];
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
+    for (int q = 0; q < 4; ++q) split_pk<PIECES>(v[r][2 * q], v[r][2 * q + 1], w[q]);
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      if (PIECES == 3) {
-        acc[rt][nt] = mfma_bf16(a[2 % PIECES][rt], b[0][nt], acc[rt][nt]);
-        acc[rt][nt] = mfma_bf16(a[0][rt], b[2 % PIECES][nt], acc[rt][nt]);
-        acc[rt][nt] = mfma_bf16(a[1 % PIECES][rt], b[1 % PIECES][nt], acc[rt][nt]);
-        acc[rt][nt] = mfma_bf16(a[1 % PIECES][rt], b[0][nt], acc[rt][nt]);
-        acc[rt][nt] = mfma_bf16(a[0][rt], b[1 % PIECES][nt], acc[rt][nt]);
-      }
-      acc[rt][nt] = mfma_bf16(a[0][rt], b[0][nt], acc[rt][nt]);
-    }
+    for (int pc = 0; pc < PIECES; ++pc)
+      a[pc][r] = __builtin_bit_cast(bf16x8, u32x4v{w[0][pc], w[1][pc], w[2][pc], w[3][pc]});
+  }
 }
 
 template <int RT, int NT, int PIECES, bool VEC>
@@ -248,10 +276,11 @@ __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, in
       for (int nt = 0; nt < NT; ++nt) b[pc][nt] = xp[pc * nfrag + ((int64_t)kb * NT + nt) * 64];
   };
   // Two register sets, two steps in flight: the products of step kb run while the loads of
-  // step kb+1 are outstanding, and the loads of step kb+2 are issued only after them
-  // (scheduling barriers keep the compiler from hoisting loads above the products, which
-  // would make the wait for one step also wait for the next).  Steps past the last are
-  // clamped to it (a harmless reload).
+  // step kb+1 are outstanding.  Step kb+2's A is loaded into step kb's registers as soon as
+  // they are split into pieces, its X fragments after step kb's products (scheduling
+  // barriers keep the compiler from hoisting loads above the products, which would make
+  // the wait for one step also wait for the next).  Steps past the last are clamped to it
+  // (a harmless reload).
   const int nfull = n >> 5;
   if (nfull > 0) {
     float v0[RT][8], v1[RT][8];
@@ -261,22 +290,34 @@ __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, in
     load_b(0, b0);
     load_a(last < 1 ? last : 1, v1);
     load_b(last < 1 ? last : 1, b1);
+    // a step's A registers are reloaded as soon as they are converted to pieces, so each
+    // A load has the matrix-core work of one more step to arrive
+    bf16x8 a[PIECES][RT];
     int kb = 0;
     for (; kb + 2 <= nfull; kb += 2) {
-      ax_products<RT, NT, PIECES>(v0, b0, acc);
+      to_pieces_rows<RT, PIECES>(v0, a);
       __builtin_amdgcn_sched_barrier(0);
       const int k2 = (kb + 2 < last) ? kb + 2 : last;
       load_a(k2, v0);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_pieces<RT, NT, PIECES, true>(a, b0, acc);
+      __builtin_amdgcn_sched_barrier(0);
       load_b(k2, b0);
       __builtin_amdgcn_sched_barrier(0);
-      ax_products<RT, NT, PIECES>(v1, b1, acc);
+      to_pieces_rows<RT, PIECES>(v1, a);
       __builtin_amdgcn_sched_barrier(0);
       const int k3 = (kb + 3 < last) ? kb + 3 : last;
       load_a(k3, v1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_pieces<RT, NT, PIECES, true>(a, b1, acc);
+      __builtin_amdgcn_sched_barrier(0);
       load_b(k3, b1);
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (kb < nfull) ax_products<RT, NT, PIECES>(v0, b0, acc);
+    if (kb < nfull) {
+      to_pieces_rows<RT, PIECES>(v0, a);
+      mfma_pieces<RT, NT, PIECES, true>(a, b0, acc);
+    }
   }
   if ((nfull << 5) < n) {
     // ragged last step: columns past n read as 0 (the packed X rows there are 0 as well)
@@ -288,7 +329,9 @@ __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, in
 #pragma unroll
       for (int e = 0; e < 8; ++e) v[rt][e] = (k0 + e < n) ? arow[rt][32 * nfull + e] : 0.f;
     load_b(nfull, b);
-    ax_products<RT, NT, PIECES>(v, b, acc);
+    bf16x8 a[PIECES][RT];
+    to_pieces_rows<RT, PIECES>(v, a);
+    mfma_pieces<RT, NT, PIECES, true>(a, b, acc);
   }
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -388,33 +431,24 @@ __device__ __forceinline__ void mx_tile(int total, int ncol, int& chunk, int& ct
 // columns cb = cw + 4i .. cb+3 of rows rb + 8g + t (t < 8); MFMA tile e takes column
 // cb + e, k-slot (g, t) row rb + 8g + t.  Full steps run without bounds tests when FC;
 // the ragged last rows of the matrix are tested.
-template <int NT, int PIECES>
-__device__ __forceinline__ void atq_products(const float (&v)[8][4],
-                                             const bf16x8 (&b)[PIECES][NT],
-                                             f32x4 (&acc)[4][NT]) {
-  bf16x8 a[PIECES][4];
+template <int PIECES>
+__device__ __forceinline__ void to_pieces_cols(const float (&v)[8][4], bf16x8 (&a)[PIECES][4]) {
+  if (PIECES == 1) {
 #pragma unroll
-  for (int t = 0; t < 8; ++t)
+    for (int t = 0; t < 8; ++t)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      __bf16 p[3];
-      to_pieces<PIECES>(v[t][e], p);
+      for (int e = 0; e < 4; ++e) a[0][e][t] = (__bf16)v[t][e];
+    return;
+  }
 #pragma unroll
-      for (int pc = 0; pc < PIECES; ++pc) a[pc][e][t] = p[pc];
-    }
+  for (int e = 0; e < 4; ++e) {
+    unsigned w[4][PIECES];
 #pragma unroll
-  for (int e = 0; e < 4; ++e)
+    for (int q = 0; q < 4; ++q) split_pk<PIECES>(v[2 * q][e], v[2 * q + 1][e], w[q]);
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      if (PIECES == 3) {
-        acc[e][nt] = mfma_bf16(a[2 % PIECES][e], b[0][nt], acc[e][nt]);
-        acc[e][nt] = mfma_bf16(a[0][e], b[2 % PIECES][nt], acc[e][nt]);
-        acc[e][nt] = mfma_bf16(a[1 % PIECES][e], b[1 % PIECES][nt], acc[e][nt]);
-        acc[e][nt] = mfma_bf16(a[1 % PIECES][e], b[0][nt], acc[e][nt]);
-        acc[e][nt] = mfma_bf16(a[0][e], b[1 % PIECES][nt], acc[e][nt]);
-      }
-      acc[e][nt] = mfma_bf16(a[0][e], b[0][nt], acc[e][nt]);
-    }
+    for (int pc = 0; pc < PIECES; ++pc)
+      a[pc][e] = __builtin_bit_cast(bf16x8, u32x4v{w[0][pc], w[1][pc], w[2][pc], w[3][pc]});
+  }
 }
 
 template <int NT, int PIECES, bool FC>
@@ -453,22 +487,32 @@ __device__ __forceinline__ void atq_rows(const float* __restrict__ A, int64_t ld
     const int64_t r1st = (r0 + 32 < last) ? r0 + 32 : last;
     load_a(r1st, v1);
     load_b(r1st, b1);
+    bf16x8 a[PIECES][4];
     int64_t rb = r0;
     for (; rb + 64 <= rfull; rb += 64) {
-      atq_products<NT, PIECES>(v0, b0, acc);
+      to_pieces_cols<PIECES>(v0, a);
       __builtin_amdgcn_sched_barrier(0);
       const int64_t r2 = (rb + 64 < last) ? rb + 64 : last;
       load_a(r2, v0);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_pieces<4, NT, PIECES, false>(a, b0, acc);
+      __builtin_amdgcn_sched_barrier(0);
       load_b(r2, b0);
       __builtin_amdgcn_sched_barrier(0);
-      atq_products<NT, PIECES>(v1, b1, acc);
+      to_pieces_cols<PIECES>(v1, a);
       __builtin_amdgcn_sched_barrier(0);
       const int64_t r3 = (rb + 96 < last) ? rb + 96 : last;
       load_a(r3, v1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_pieces<4, NT, PIECES, false>(a, b1, acc);
+      __builtin_amdgcn_sched_barrier(0);
       load_b(r3, b1);
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (rb < rfull) atq_products<NT, PIECES>(v0, b0, acc);
+    if (rb < rfull) {
+      to_pieces_cols<PIECES>(v0, a);
+      mfma_pieces<4, NT, PIECES, false>(a, b0, acc);
+    }
   }
   if (rfull < r1) {
     // ragged last rows (only the chunk that ends at m): rows past r1 read as 0
@@ -482,7 +526,9 @@ __device__ __forceinline__ void atq_rows(const float* __restrict__ A, int64_t ld
       for (int e = 0; e < 4; ++e) v[t][e] = (row < r1 && cb + e < n) ? p[e] : 0.f;
     }
     load_b(rfull, b);
-    atq_products<NT, PIECES>(v, b, acc);
+    bf16x8 a[PIECES][4];
+    to_pieces_cols<PIECES>(v, a);
+    mfma_pieces<4, NT, PIECES, false>(a, b, acc);
   }
 }
 
