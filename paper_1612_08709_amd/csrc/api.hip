@@ -354,7 +354,7 @@ namespace {
 
 struct LowrankWs {
   TsqrPlan pY, pZ;
-  double *X, *Y, *Z, *Zraw, *Qy, *part, *I, *P, *sig, *W, *Wk, *G, *ortho, *Tq, *Rc;
+  double *X, *Y, *Z, *Zraw, *part, *I, *P, *sig, *W, *Wk, *G, *ortho, *Tq, *Rc;
   void* pack;
   void* Acopy;  // bfloat16 copy of A for the mixed power steps (or null)
   int* gate;
@@ -381,9 +381,7 @@ LowrankWs lowrank_layout(int64_t m, int64_t n, int k, int l, void* work, bool mi
   if (mixed && mixed_partials(m, n, l) > np) np = mixed_partials(m, n, l);
   w.part = c.take<double>(np);
   w.pack = nullptr;
-  w.Qy = nullptr;
   if (mixed) {
-    w.Qy = c.take<double>((size_t)m * l);
     size_t pb = mixed_pack_bytes(m, l);
     if (mixed_pack_bytes(n, l) > pb) pb = mixed_pack_bytes(n, l);
     w.pack = c.take<char>(pb);
@@ -511,13 +509,16 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
     copy_ready = w.Acopy != nullptr;
     return gemm_ax_bf16p(A32, lda, m, n, w.pack, li, w.Y, li, w.Acopy, s, TSSVD_PROF_AX_BF16);
   };
+  // Qs == nullptr: the operand is already packed (bfloat16, power steps)
   auto atq = [&](const double* Qs, bool last, double* Zout) -> hipError_t {
     if (!mixed)
       return gemm_atq_f64(A, a_dtype, lda, m, n, Qs, li, li, Zout, li, w.part, s,
                           TSSVD_PROF_ATQ);
     const int kind = !last ? MIX_BF16 : (f32_final ? MIX_F32_ROWS : MIX_BF16X3);
-    hipError_t e = pack_operand(Qs, m, li, li, kind, w.pack, s);
-    if (e != hipSuccess) return e;
+    if (Qs) {
+      hipError_t e = pack_operand(Qs, m, li, li, kind, w.pack, s);
+      if (e != hipSuccess) return e;
+    }
     if (!last && copy_ready)
       return gemm_atq_bf16c(w.Acopy, m, n, w.pack, li, Zout, li, w.part, s,
                             TSSVD_PROF_ATQ_BF16C);
@@ -527,14 +528,15 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   // Algorithm 5: subspace iteration.  Intermediate bases: Q_j = Y R_j^-1 and
   // Q~_j = Z R~_j^-1 (or the explicit Householder Q when R is ill-conditioned).  In FP64
   // the product uses Y itself, A^* Q_j = (A^* Y) R_j^-1; in mixed precision Q_j is formed
-  // first, because bfloat16 rounding of Y's entries would be amplified by R_j^-1.
+  // first (in FP64, written straight out as bfloat16 operand fragments), because
+  // bfloat16 rounding of Y's entries would be amplified by R_j^-1.
   int* use_q = w.gate + 1;
   TRY(ax(w.X, q == 0));                                                        // A Q~_0
   for (int64_t j = 0; j < q; ++j) {
     TRY(basis_via_r(w.pY, w.Y, m, li, w.I, w.Tq, w.G, w.Rc, w.part, use_q, s));  // Q_j = Y T
     if (mixed) {
-      TRY(gemm_ax_f64(w.Y, TSSVD_F64, l, m, l, w.Tq, li, li, w.Qy, li, s));   // Q_j
-      TRY(atq(w.Qy, false, w.Z));                                              // A^* Q_j
+      TRY(gemm_ax_f64_pack_bf16(w.Y, l, m, w.Tq, li, li, w.pack, s));         // Q_j, packed
+      TRY(atq(nullptr, false, w.Z));                                           // A^* Q_j
     } else {
       TRY(atq(w.Y, false, w.Zraw));                                            // A^* Y
       TRY(gemm_ax_f64(w.Zraw, TSSVD_F64, l, n, l, w.Tq, li, li, w.Z, li, s)); // A^* Q_j

@@ -21,6 +21,7 @@
 namespace tsv {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 
 __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -56,11 +57,18 @@ __device__ __forceinline__ void load4(const float* p, bool full, int valid, doub
   }
 }
 
-template <int RT, int NT, typename TA>
+// PACK (RT = 2, so wave w's rows are the 32-row block kb = blockIdx*4 + w): instead of
+// storing Y, write the bfloat16 B-operand fragments of Y used by the mixed A^T Q kernels,
+//   P[(kb*NT + nt)*64 + lane][e] = bf16(Y[32 kb + 8 (lane/16) + e][16 nt + lane%16]),
+// each entry rounded once from its float64 value, exactly what packing the stored Y gives.
+// The MFMA result rows 16 rt + 4 r + g of a lane become the fragment rows 8 g + e through
+// a bfloat16 transpose in LDS.
+template <int RT, int NT, typename TA, bool PACK = false>
 __global__ __launch_bounds__(256) void k_gemm_ax_f64(const TA* __restrict__ A, int64_t lda,
                                                      int64_t m, int n,
                                                      const double* __restrict__ X, int ldx,
-                                                     int l, double* __restrict__ Y, int ldy) {
+                                                     int l, double* __restrict__ Y, int ldy,
+                                                     bf16x8_t* __restrict__ P = nullptr) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int64_t rbase = (int64_t)blockIdx.x * (64 * RT) + (int64_t)wave * (16 * RT);
@@ -118,6 +126,25 @@ __global__ __launch_bounds__(256) void k_gemm_ax_f64(const TA* __restrict__ A, i
 #pragma unroll
       for (int s = 0; s < 4; ++s) a[rt][s] = an[rt][s];
   }
+  if constexpr (PACK) {
+    static_assert(RT == 2, "one 32-row block per wave");
+    // qs[wave][nt][col i][row 0..31]: a lane's eight fragment rows are 16 contiguous bytes
+    __shared__ __attribute__((aligned(16))) __bf16 qs[4][NT][16][32];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) qs[wave][nt][li][16 * rt + 4 * r + g] = (__bf16)acc[rt][nt][r];
+    __syncthreads();
+    if (rbase < m) {
+      const int64_t kb = rbase >> 5;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        P[(kb * NT + nt) * 64 + lane] = *reinterpret_cast<const bf16x8_t*>(&qs[wave][nt][li][8 * g]);
+    }
+    return;
+  }
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -129,6 +156,30 @@ __global__ __launch_bounds__(256) void k_gemm_ax_f64(const TA* __restrict__ A, i
         if (row < m && col < l) Y[row * ldy + col] = acc[rt][nt][r];
       }
     }
+}
+
+template <int NT>
+static void launch_ax_pack(const double* Y, int64_t ldy, int64_t m, const double* T, int ldt,
+                           int l, void* P, hipStream_t s) {
+  constexpr int RT = 2;
+  const int64_t grid = (m + 64 * RT - 1) / (64 * RT);
+  hipLaunchKernelGGL((k_gemm_ax_f64<RT, NT, double, true>), dim3((unsigned)grid), dim3(256), 0,
+                     s, Y, ldy, m, l, T, ldt, l, (double*)nullptr, 0, (bf16x8_t*)P);
+}
+
+hipError_t gemm_ax_f64_pack_bf16(const double* Y, int64_t ldy, int64_t m, const double* T,
+                                 int ldt, int l, void* P, hipStream_t s) {
+  switch ((l + 15) / 16) {
+    case 1: launch_ax_pack<1>(Y, ldy, m, T, ldt, l, P, s); break;
+    case 2: launch_ax_pack<2>(Y, ldy, m, T, ldt, l, P, s); break;
+    case 3: launch_ax_pack<3>(Y, ldy, m, T, ldt, l, P, s); break;
+    case 4: launch_ax_pack<4>(Y, ldy, m, T, ldt, l, P, s); break;
+    case 5: launch_ax_pack<5>(Y, ldy, m, T, ldt, l, P, s); break;
+    case 6: launch_ax_pack<6>(Y, ldy, m, T, ldt, l, P, s); break;
+    case 7: launch_ax_pack<7>(Y, ldy, m, T, ldt, l, P, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <int NT, typename TA>
@@ -333,9 +384,123 @@ static hipError_t atq_dispatch(const TA* A, int64_t lda, int64_t m, int64_t n, c
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- G = Y^T Y
+// Gram of a tall FP64 matrix with l <= 16*NT <= 64 columns (the bases of the power steps,
+// the orthonormality checks).  Tile (ti, tj) of G is the product of Y's column tiles ti
+// and tj, so one load serves both operands: per group of four rows, lane (i, g) loads
+// Y[row0 + g][16t + i] (t < NT), the A operand of tile t (a[i][k = g]) and its B operand
+// (b[k = g][j = i]) at once.  Only the tiles ti <= tj are formed.  Workgroup c takes rows
+// [c*chunk, (c+1)*chunk); its wave w the four-row groups w, w+4, ...; the four waves'
+// sums are added in a fixed order through LDS and the workgroup writes its partial Gram
+// with both (i, j) and (j, i) set from the entry i <= j, so every partial, and the reduced
+// G, is exactly symmetric.
+constexpr int GRAM_WG_MAX = 512;
+constexpr int GRAM_DEPTH = 4;  // four-row groups in flight per wave
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ Y, int64_t rows,
+                                                  int l, int ldy, int64_t chunk,
+                                                  double* __restrict__ part) {
+  constexpr int NTILE = NT * (NT + 1) / 2;
+  __shared__ double red[2][NTILE * 4 * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = (r0 + chunk < rows) ? r0 + chunk : rows;
+  f64x4 acc[NTILE];
+#pragma unroll
+  for (int t = 0; t < NTILE; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  auto load = [&](int64_t grp, double (&y)[NT]) {
+    const int64_t row = r0 + 4 * grp + g;
+    const bool ok = row < r1;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int col = 16 * t + li;
+      y[t] = (ok && col < l) ? Y[row * ldy + col] : 0.0;
+    }
+  };
+  const int64_t ngrp = (r1 - r0 + 3) / 4;  // four-row groups of the chunk (r1 > r0)
+  double y[GRAM_DEPTH][NT];
+#pragma unroll
+  for (int d = 0; d < GRAM_DEPTH; ++d) load(wave + 4 * d, y[d]);
+  for (int64_t gb = wave; gb < ngrp; gb += 4 * GRAM_DEPTH) {
+#pragma unroll
+    for (int d = 0; d < GRAM_DEPTH; ++d) {
+      int t = 0;
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < NT; ++tj, ++t) acc[t] = mfma_f64(y[d][ti], y[d][tj], acc[t]);
+      // groups past the chunk load zeros (their rows fail the row test)
+      load(gb + 4 * (d + GRAM_DEPTH), y[d]);
+    }
+  }
+  // fixed-order sum of the four waves: (w0 + w2) + (w1 + w3)
+  auto put = [&](int slot) {
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[slot][(t * 4 + r) * 64 + lane] = acc[t][r];
+  };
+  auto add = [&](int slot) {
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[t][r] += red[slot][(t * 4 + r) * 64 + lane];
+  };
+  if (wave >= 2) put(wave - 2);
+  __syncthreads();
+  if (wave < 2) add(wave);
+  __syncthreads();
+  if (wave == 1) put(0);
+  __syncthreads();
+  if (wave != 0) return;
+  add(0);
+  double* P = part + (int64_t)blockIdx.x * l * l;
+  int t = 0;
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+    for (int tj = ti; tj < NT; ++tj, ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * ti + 4 * r + g, j = 16 * tj + li;
+        if (i <= j && j < l) {
+          P[(int64_t)i * l + j] = acc[t][r];
+          P[(int64_t)j * l + i] = acc[t][r];
+        }
+      }
+}
+
+static int gram_grid(int64_t rows, int64_t& chunk) {
+  int64_t want = (rows + 63) / 64;
+  if (want > GRAM_WG_MAX) want = GRAM_WG_MAX;
+  chunk = (rows + want - 1) / want;
+  chunk = (chunk + 15) / 16 * 16;
+  return (int)((rows + chunk - 1) / chunk);
+}
+
+static hipError_t gram_f64(const double* Y, int64_t rows, int l, int ldy, double* G, int ldg,
+                           double* part, hipStream_t s) {
+  int64_t chunk;
+  const int nwg = gram_grid(rows, chunk);
+  switch ((l + 15) / 16) {
+    case 1: hipLaunchKernelGGL((k_gram_f64<1>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
+    case 2: hipLaunchKernelGGL((k_gram_f64<2>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
+    case 3: hipLaunchKernelGGL((k_gram_f64<3>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
+    case 4: hipLaunchKernelGGL((k_gram_f64<4>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return reduce_chunks(part, nwg, l, l, G, ldg, s);
+}
+
 hipError_t gemm_atq_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int64_t n,
                         const double* Q, int ldq, int l, double* Z, int ldz, double* part,
                         hipStream_t s, int prof) {
+  if (a_dtype == TSSVD_F64 && A == (const void*)Q && lda == ldq && n == l && l <= 64 && m > 0)
+    return gram_f64(Q, m, l, ldq, Z, ldz, part, s);  // partials fit: nwg <= atq chunks
   prof_begin(prof, s);
   hipError_t e = (a_dtype == TSSVD_F64)
                      ? atq_dispatch((const double*)A, lda, m, n, Q, ldq, l, part, s)

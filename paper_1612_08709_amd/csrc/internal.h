@@ -82,6 +82,10 @@ hipError_t gemm_atq_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int6
                         const double* Q, int ldq, int l, double* Z, int ldz, double* part,
                         hipStream_t s, int prof = -1);
 
+// Q = Y T (Y m x l float64, T l x l) written as the bfloat16 fragments of Q that
+// pack_operand(Q, m, l, l, MIX_BF16, P) produces (bitwise the same), Q never stored.
+hipError_t gemm_ax_f64_pack_bf16(const double* Y, int64_t ldy, int64_t m, const double* T,
+                                 int ldt, int l, void* P, hipStream_t s);
 hipError_t reduce_chunks(const double* part, int nchunk, int64_t n, int l, double* Z, int ldz,
                          hipStream_t s);
 
