@@ -763,12 +763,22 @@ __global__ __launch_bounds__(256) void k_ax_bf16p(const float* __restrict__ A, i
 // lane reads its 16 consecutive values of a row as two adjacent 16-byte fragments, used by
 // the two MFMAs as they are; same products in the same order as k_ax_bf16p, so the result
 // is bitwise that of rounding the float32 A in the pass.  Rows past m read row m-1.
+//
+// The four waves need the same X fragments, so a group's fragments (2*NT*64, contiguous in
+// Xp) are read from memory once per workgroup: thread t loads fragments t, t + 256, ... of
+// group kg + 2 while group kg computes, and stores them to LDS slot kg & 1 when group kg + 2
+// comes up; after a barrier every wave reads its B operands there.  Slot s is rewritten
+// only after the barrier of the next group, which every wave reaches after its reads of s.
 template <int RT, int NT>
 __global__ __launch_bounds__(256) void k_ax_bf16c(const bf16x8* __restrict__ Ac, int64_t ldc8,
                                                   int64_t m, int ngroups,
                                                   const bf16x8* __restrict__ Xp, int l,
                                                   double* __restrict__ Y, int ldy) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int FR = 2 * NT * 64;         // X fragments per group
+  constexpr int FPT = (FR + 255) / 256;   // loaded per thread
+  __shared__ bf16x8 xs[2][FR];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int64_t rbase = (int64_t)blockIdx.x * (64 * RT) + (int64_t)wave * (16 * RT);
   f32x4 acc[RT][NT];
@@ -782,17 +792,26 @@ __global__ __launch_bounds__(256) void k_ax_bf16c(const bf16x8* __restrict__ Ac,
     const int64_t row = rbase + 16 * rt + li;
     arow[rt] = Ac + (row < m ? row : m - 1) * ldc8 + 2 * g;
   }
-  const bf16x8* xp = Xp + lane;
-  auto load = [&](int kg, bf16x8 (&a)[2][RT], bf16x8 (&b)[2][NT]) {
+  auto load = [&](int kg, bf16x8 (&a)[2][RT], bf16x8 (&x)[FPT]) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) a[j][rt] = arow[rt][8 * kg + j];
+    const bf16x8* src = Xp + (int64_t)kg * FR;
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) b[j][nt] = xp[((int64_t)(2 * kg + j) * NT + nt) * 64];
-    }
+    for (int u = 0; u < FPT; ++u)
+      if (FR % 256 == 0 || tid + 256 * u < FR) x[u] = src[tid + 256 * u];
   };
-  auto products = [&](const bf16x8 (&a)[2][RT], const bf16x8 (&b)[2][NT]) {
+  auto products = [&](int slot, const bf16x8 (&a)[2][RT], const bf16x8 (&x)[FPT]) {
+#pragma unroll
+    for (int u = 0; u < FPT; ++u)
+      if (FR % 256 == 0 || tid + 256 * u < FR) xs[slot][tid + 256 * u] = x[u];
+    __syncthreads();
+    bf16x8 b[2][NT];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) b[j][nt] = xs[slot][(j * NT + nt) * 64 + lane];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -801,22 +820,22 @@ __global__ __launch_bounds__(256) void k_ax_bf16c(const bf16x8* __restrict__ Ac,
         for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mfma_bf16(a[j][rt], b[j][nt], acc[rt][nt]);
   };
   // two register sets, two groups in flight (as in k_ax_bf16)
-  bf16x8 a0[2][RT], a1[2][RT], b0[2][NT], b1[2][NT];
+  bf16x8 a0[2][RT], a1[2][RT], x0[FPT], x1[FPT];
   const int last = ngroups - 1;
-  load(0, a0, b0);
-  load(last < 1 ? last : 1, a1, b1);
+  load(0, a0, x0);
+  load(last < 1 ? last : 1, a1, x1);
   int kg = 0;
   for (; kg + 2 <= ngroups; kg += 2) {
-    products(a0, b0);
+    products(0, a0, x0);
     __builtin_amdgcn_sched_barrier(0);
-    load((kg + 2 < last) ? kg + 2 : last, a0, b0);
+    load((kg + 2 < last) ? kg + 2 : last, a0, x0);
     __builtin_amdgcn_sched_barrier(0);
-    products(a1, b1);
+    products(1, a1, x1);
     __builtin_amdgcn_sched_barrier(0);
-    load((kg + 3 < last) ? kg + 3 : last, a1, b1);
+    load((kg + 3 < last) ? kg + 3 : last, a1, x1);
     __builtin_amdgcn_sched_barrier(0);
   }
-  if (kg < ngroups) products(a0, b0);
+  if (kg < ngroups) products(0, a0, x0);
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -855,60 +874,92 @@ __device__ __forceinline__ void atqc_products(const uint2 (&v)[8], const bf16x8 
     for (int nt = 0; nt < NT; ++nt) acc[e][nt] = mfma_bf16(a[e], b[nt], acc[e][nt]);
 }
 
+// The Q fragments of a 32-row step (NT*64, contiguous) are shared by the four waves through
+// LDS as in k_ax_bf16c, two steps per barrier, so every wave takes part in the loop; a
+// wave whose columns lie past n reads no A (zeros) and stores nothing.
 template <int NT>
 __global__ __launch_bounds__(256) void k_atq_bf16c(const __bf16* __restrict__ Ac, int64_t ldc,
                                                    int64_t m, int n,
                                                    const bf16x8* __restrict__ Qp, int l,
                                                    int ncol, int nchunk, int64_t chunk_rows,
                                                    double* __restrict__ part) {
+  constexpr int FR = NT * 64;             // Q fragments per step
+  constexpr int FPT = (FR + 255) / 256;   // loaded per thread
+  __shared__ bf16x8 qs[2][2][FR];
   int chunk, ct;
   bool ok;
   mx_tile(ncol * nchunk, ncol, chunk, ct, ok);
   if (!ok) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int cw = ct * MX_COLS + 64 * wave;
-  if (cw >= n) return;
+  const bool wact = cw < n;
   const int64_t r0 = (int64_t)chunk * chunk_rows;  // chunk_rows is a multiple of 32
   const int64_t r1 = (r0 + chunk_rows < m) ? r0 + chunk_rows : m;
   const int cb = cw + 4 * li;
-  const bool cok = cb < ldc;  // ldc is a multiple of 32, so cb + 4 <= ldc
+  const bool cok = wact && cb < ldc;  // ldc is a multiple of 32, so cb + 4 <= ldc
   f32x4 acc[4][NT];
 #pragma unroll
   for (int e = 0; e < 4; ++e)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[e][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
   const bf16x8* qp = Qp + lane;
-  auto load = [&](int64_t rb, uint2 (&v)[8], bf16x8 (&b)[NT]) {
+  // Q shares first: waiting for a step's shares then does not wait for its A
+  auto load = [&](int64_t rb, uint2 (&v)[8], bf16x8 (&x)[FPT]) {
+    const bf16x8* src = Qp + (rb >> 5) * FR;
+#pragma unroll
+    for (int u = 0; u < FPT; ++u)
+      if (FR % 256 == 0 || tid + 256 * u < FR) x[u] = src[tid + 256 * u];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const __bf16* p = Ac + (rb + 8 * g + t) * ldc + cb;
       v[t] = cok ? *reinterpret_cast<const uint2*>(p) : make_uint2(0u, 0u);
     }
-    const int64_t kb = rb >> 5;
+  };
+  // both steps of a 64-row pair are staged together: one barrier per pair
+  auto stage = [&](int slot, const bf16x8 (&x0)[FPT], const bf16x8 (&x1)[FPT]) {
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) b[nt] = qp[(kb * NT + nt) * 64];
+    for (int u = 0; u < FPT; ++u)
+      if (FR % 256 == 0 || tid + 256 * u < FR) {
+        qs[slot][0][tid + 256 * u] = x0[u];
+        qs[slot][1][tid + 256 * u] = x1[u];
+      }
+    __syncthreads();
+  };
+  auto products = [&](int slot, int h, const uint2 (&v)[8]) {
+    bf16x8 b[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) b[nt] = qs[slot][h][nt * 64 + lane];
+    atqc_products<NT>(v, b, acc);
   };
   const int64_t rfull = r0 + (((r1 - r0) >> 5) << 5);
   if (rfull > r0) {
     uint2 v0[8], v1[8];
-    bf16x8 b0[NT], b1[NT];
+    bf16x8 x0[FPT], x1[FPT];
     const int64_t last = rfull - 32;
-    load(r0, v0, b0);
-    load((r0 + 32 < last) ? r0 + 32 : last, v1, b1);
+    load(r0, v0, x0);
+    load((r0 + 32 < last) ? r0 + 32 : last, v1, x1);
     int64_t rb = r0;
+    int slot = 0;
     for (; rb + 64 <= rfull; rb += 64) {
-      atqc_products<NT>(v0, b0, acc);
+      stage(slot, x0, x1);
+      products(slot, 0, v0);
       __builtin_amdgcn_sched_barrier(0);
-      load((rb + 64 < last) ? rb + 64 : last, v0, b0);
+      load((rb + 64 < last) ? rb + 64 : last, v0, x0);
       __builtin_amdgcn_sched_barrier(0);
-      atqc_products<NT>(v1, b1, acc);
+      products(slot, 1, v1);
       __builtin_amdgcn_sched_barrier(0);
-      load((rb + 96 < last) ? rb + 96 : last, v1, b1);
+      load((rb + 96 < last) ? rb + 96 : last, v1, x1);
       __builtin_amdgcn_sched_barrier(0);
+      slot ^= 1;
     }
-    if (rb < rfull) atqc_products<NT>(v0, b0, acc);
+    if (rb < rfull) {
+      stage(slot, x0, x0);
+      products(slot, 0, v0);
+    }
   }
+  if (!wact) return;
   if (rfull < r1) {
     // ragged last rows (only the chunk that ends at m): rows past r1 read as 0
     uint2 v[8];
