@@ -275,14 +275,84 @@ __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, in
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) b[pc][nt] = xp[pc * nfrag + ((int64_t)kb * NT + nt) * 64];
   };
+  // One piece: X fragments are shared by the four waves: a step's NT*64 fragments are loaded
+  // once per workgroup (each thread its share, with the step's A), stored to LDS slot
+  // kb & 1 when the step comes up and read back by every wave after a barrier.  Slot s is
+  // rewritten only after the next step's barrier, which every wave reaches after its reads.
+  constexpr int FS = NT * 64;            // fragments per piece and step
+  constexpr int FR = PIECES * FS;        // per step
+  constexpr int FPT = (FR + 255) / 256;  // loaded per thread
+  __shared__ bf16x8 xs[2][FR];
+  const int tid = threadIdx.x;
+  auto load_x = [&](int kb, bf16x8 (&x)[FPT]) {
+#pragma unroll
+    for (int u = 0; u < FPT; ++u) {
+      const int f = tid + 256 * u;
+      if (FR % 256 == 0 || f < FR) {
+        const int pc = f / FS;
+        x[u] = Xp[pc * nfrag + (int64_t)kb * FS + (f - pc * FS)];
+      }
+    }
+  };
+  auto stage = [&](int slot, const bf16x8 (&x)[FPT], bf16x8 (&b)[PIECES][NT]) {
+#pragma unroll
+    for (int u = 0; u < FPT; ++u) {
+      const int f = tid + 256 * u;
+      if (FR % 256 == 0 || f < FR) xs[slot][f] = x[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int pc = 0; pc < PIECES; ++pc)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) b[pc][nt] = xs[slot][pc * FS + nt * 64 + lane];
+  };
   // Two register sets, two steps in flight: the products of step kb run while the loads of
-  // step kb+1 are outstanding.  Step kb+2's A is loaded into step kb's registers as soon as
-  // they are split into pieces, its X fragments after step kb's products (scheduling
-  // barriers keep the compiler from hoisting loads above the products, which would make
-  // the wait for one step also wait for the next).  Steps past the last are clamped to it
-  // (a harmless reload).
+  // step kb+1 are outstanding.  Step kb+2's A and X shares are loaded into step kb's
+  // registers as soon as A is split into pieces and the shares are in LDS (scheduling
+  // barriers keep the compiler from hoisting loads above the products, which would make the
+  // wait for one step also wait for the next).  Steps past the last are clamped to it (a
+  // harmless reload).
   const int nfull = n >> 5;
-  if (nfull > 0) {
+  if constexpr (PIECES == 1) {
+    if (nfull > 0) {
+      float v0[RT][8], v1[RT][8];
+      bf16x8 x0[FPT], x1[FPT];
+      const int last = nfull - 1;
+      load_a(0, v0);
+      load_x(0, x0);
+      load_a(last < 1 ? last : 1, v1);
+      load_x(last < 1 ? last : 1, x1);
+      bf16x8 a[PIECES][RT], b[PIECES][NT];
+      int kb = 0;
+      for (; kb + 2 <= nfull; kb += 2) {
+        stage(0, x0, b);
+        to_pieces_rows<RT, PIECES>(v0, a);
+        __builtin_amdgcn_sched_barrier(0);
+        const int k2 = (kb + 2 < last) ? kb + 2 : last;
+        load_a(k2, v0);
+        load_x(k2, x0);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_pieces<RT, NT, PIECES, true>(a, b, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        stage(1, x1, b);
+        to_pieces_rows<RT, PIECES>(v1, a);
+        __builtin_amdgcn_sched_barrier(0);
+        const int k3 = (kb + 3 < last) ? kb + 3 : last;
+        load_a(k3, v1);
+        load_x(k3, x1);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_pieces<RT, NT, PIECES, true>(a, b, acc);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (kb < nfull) {
+        stage(0, x0, b);
+        to_pieces_rows<RT, PIECES>(v0, a);
+        mfma_pieces<RT, NT, PIECES, true>(a, b, acc);
+      }
+    }
+  } else if (nfull > 0) {
+    // three pieces (occupancy 1, long steps): each wave loads its own X fragments, which
+    // measured faster than a barrier per step
     float v0[RT][8], v1[RT][8];
     bf16x8 b0[PIECES][NT], b1[PIECES][NT];
     const int last = nfull - 1;
@@ -290,8 +360,6 @@ __global__ __launch_bounds__(256) void k_ax_bf16(const float* __restrict__ A, in
     load_b(0, b0);
     load_a(last < 1 ? last : 1, v1);
     load_b(last < 1 ? last : 1, b1);
-    // a step's A registers are reloaded as soon as they are converted to pieces, so each
-    // A load has the matrix-core work of one more step to arrive
     bf16x8 a[PIECES][RT];
     int kb = 0;
     for (; kb + 2 <= nfull; kb += 2) {
@@ -451,8 +519,10 @@ __device__ __forceinline__ void to_pieces_cols(const float (&v)[8][4], bf16x8 (&
   }
 }
 
+// Each wave loads its own Q fragments (three pieces: occupancy 1 and long steps, where a
+// barrier per step measured slower).
 template <int NT, int PIECES, bool FC>
-__device__ __forceinline__ void atq_rows(const float* __restrict__ A, int64_t lda, int n,
+__device__ __forceinline__ void atq_rows_own(const float* __restrict__ A, int64_t lda, int n,
                                          int cb, int g, int64_t r0, int64_t r1,
                                          const bf16x8* __restrict__ qp, int64_t nfrag,
                                          f32x4 (&acc)[4][NT]) {
@@ -532,6 +602,119 @@ __device__ __forceinline__ void atq_rows(const float* __restrict__ A, int64_t ld
   }
 }
 
+// One piece: the Q fragments of a 32-row step (NT*64) are shared by the four waves through
+// a two-slot LDS ring as in Y = A X, so all four waves run the loop; a wave with wact false
+// (its columns lie past n) loads no A.
+template <int NT, int PIECES, bool FC>
+__device__ __forceinline__ void atq_rows(const float* __restrict__ A, int64_t lda, int n,
+                                         int cb, int g, bool wact, int64_t r0, int64_t r1,
+                                         const bf16x8* __restrict__ Qp, int64_t nfrag,
+                                         bf16x8 (*qs)[PIECES * NT * 64], f32x4 (&acc)[4][NT]) {
+  static_assert(PIECES == 1, "three pieces use atq_rows_own");
+  constexpr int FS = NT * 64;
+  constexpr int FR = PIECES * FS;
+  constexpr int FPT = (FR + 255) / 256;
+  const int tid = threadIdx.x, lane = tid & 63;
+  auto load_a = [&](int64_t rb, float (&v)[8][4]) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const float* p = A + (rb + 8 * g + t) * lda + cb;
+      if (FC) {
+        float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (wact) x = *reinterpret_cast<const float4*>(p);
+        v[t][0] = x.x; v[t][1] = x.y; v[t][2] = x.z; v[t][3] = x.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[t][e] = (wact && cb + e < n) ? p[e] : 0.f;
+      }
+    }
+  };
+  auto load_x = [&](int64_t rb, bf16x8 (&x)[FPT]) {
+    const int64_t kb = rb >> 5;
+#pragma unroll
+    for (int u = 0; u < FPT; ++u) {
+      const int f = tid + 256 * u;
+      if (FR % 256 == 0 || f < FR) {
+        const int pc = f / FS;
+        x[u] = Qp[pc * nfrag + kb * FS + (f - pc * FS)];
+      }
+    }
+  };
+  auto stage = [&](int slot, const bf16x8 (&x)[FPT], bf16x8 (&b)[PIECES][NT]) {
+#pragma unroll
+    for (int u = 0; u < FPT; ++u) {
+      const int f = tid + 256 * u;
+      if (FR % 256 == 0 || f < FR) qs[slot][f] = x[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int pc = 0; pc < PIECES; ++pc)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) b[pc][nt] = qs[slot][pc * FS + nt * 64 + lane];
+  };
+  const int64_t rfull = r0 + (((r1 - r0) >> 5) << 5);
+  if constexpr (PIECES == 1) {
+    if (rfull > r0) {
+      // two register sets, two steps in flight (as in Y = A X)
+      float v0[8][4], v1[8][4];
+      bf16x8 x0[FPT], x1[FPT];
+      const int64_t last = rfull - 32;
+      load_a(r0, v0);
+      load_x(r0, x0);
+      const int64_t r1st = (r0 + 32 < last) ? r0 + 32 : last;
+      load_a(r1st, v1);
+      load_x(r1st, x1);
+      bf16x8 a[PIECES][4], b[PIECES][NT];
+      int64_t rb = r0;
+      for (; rb + 64 <= rfull; rb += 64) {
+        stage(0, x0, b);
+        to_pieces_cols<PIECES>(v0, a);
+        __builtin_amdgcn_sched_barrier(0);
+        const int64_t r2 = (rb + 64 < last) ? rb + 64 : last;
+        load_a(r2, v0);
+        load_x(r2, x0);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_pieces<4, NT, PIECES, false>(a, b, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        stage(1, x1, b);
+        to_pieces_cols<PIECES>(v1, a);
+        __builtin_amdgcn_sched_barrier(0);
+        const int64_t r3 = (rb + 96 < last) ? rb + 96 : last;
+        load_a(r3, v1);
+        load_x(r3, x1);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_pieces<4, NT, PIECES, false>(a, b, acc);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (rb < rfull) {
+        stage(0, x0, b);
+        to_pieces_cols<PIECES>(v0, a);
+        mfma_pieces<4, NT, PIECES, false>(a, b, acc);
+      }
+    }
+  }
+  if (rfull < r1) {
+    // ragged last rows (only the chunk that ends at m): rows past r1 read as 0
+    float v[8][4];
+    bf16x8 b[PIECES][NT];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t row = rfull + 8 * g + t;
+      const float* p = A + row * lda + cb;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[t][e] = (wact && row < r1 && cb + e < n) ? p[e] : 0.f;
+    }
+    const int64_t kb = rfull >> 5;
+#pragma unroll
+    for (int pc = 0; pc < PIECES; ++pc)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) b[pc][nt] = Qp[pc * nfrag + kb * FS + nt * 64 + lane];
+    bf16x8 a[PIECES][4];
+    to_pieces_cols<PIECES>(v, a);
+    mfma_pieces<4, NT, PIECES, false>(a, b, acc);
+  }
+}
+
 // FC: every wave's 64 columns lie inside A and rows are 16-byte aligned (n a multiple of
 // 64, A 16-byte aligned, lda a multiple of 4); otherwise every load is tested.
 template <int NT, int PIECES, bool FC>
@@ -547,16 +730,23 @@ __global__ __launch_bounds__(256) void k_atq_bf16(const float* __restrict__ A, i
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int cw = ct * MX_COLS + 64 * wave;
-  if (cw >= n) return;
+  const bool wact = cw < n;
   const int64_t r0 = (int64_t)chunk * chunk_rows;  // chunk_rows is a multiple of 32
   const int64_t r1 = (r0 + chunk_rows < m) ? r0 + chunk_rows : m;
   const int cb = cw + 4 * li;
+  __shared__ bf16x8 qs[2][PIECES == 1 ? NT * 64 : 1];
   f32x4 acc[4][NT];
 #pragma unroll
   for (int e = 0; e < 4; ++e)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[e][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  atq_rows<NT, PIECES, FC>(A, lda, n, cb, g, r0, r1, Qp + lane, nfrag, acc);
+  if constexpr (PIECES == 1) {
+    atq_rows<NT, PIECES, FC>(A, lda, n, cb, g, wact, r0, r1, Qp, nfrag, qs, acc);
+    if (!wact) return;
+  } else {
+    if (!wact) return;
+    atq_rows_own<NT, PIECES, FC>(A, lda, n, cb, g, r0, r1, Qp + lane, nfrag, acc);
+  }
   double* P = part + (int64_t)chunk * n * l;
 #pragma unroll
   for (int e = 0; e < 4; ++e)
@@ -708,31 +898,58 @@ __global__ __launch_bounds__(256) void k_ax_bf16p(const float* __restrict__ A, i
         for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mfma_bf16(a[j], b[j][nt], acc[rt][nt]);
     }
   };
+  // X fragments of a group (2*NT*64, contiguous) are shared by the four waves through a
+  // two-slot LDS ring, as in k_ax_bf16c.
+  constexpr int FR = 2 * NT * 64;
+  constexpr int FPT = (FR + 255) / 256;
+  __shared__ bf16x8 xs[2][FR];
+  const int tid = threadIdx.x;
+  auto load_x = [&](int kg, bf16x8 (&x)[FPT]) {
+    const bf16x8* src = Xp + (int64_t)kg * FR;
+#pragma unroll
+    for (int u = 0; u < FPT; ++u)
+      if (FR % 256 == 0 || tid + 256 * u < FR) x[u] = src[tid + 256 * u];
+  };
+  auto stage = [&](int slot, const bf16x8 (&x)[FPT], bf16x8 (&b)[2][NT]) {
+#pragma unroll
+    for (int u = 0; u < FPT; ++u)
+      if (FR % 256 == 0 || tid + 256 * u < FR) xs[slot][tid + 256 * u] = x[u];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) b[j][nt] = xs[slot][(j * NT + nt) * 64 + lane];
+  };
   const int nfull = n >> 6;
   if (nfull > 0) {
     float v0[RT][16], v1[RT][16];
-    bf16x8 b0[2][NT], b1[2][NT];
+    bf16x8 x0[FPT], x1[FPT], b[2][NT];
     const int last = nfull - 1;
     load_a(0, v0);
-    load_b(0, b0);
+    load_x(0, x0);
     load_a(last < 1 ? last : 1, v1);
-    load_b(last < 1 ? last : 1, b1);
+    load_x(last < 1 ? last : 1, x1);
     int kg = 0;
     for (; kg + 2 <= nfull; kg += 2) {
-      products(v0, b0, kg);
+      stage(0, x0, b);
+      products(v0, b, kg);
       __builtin_amdgcn_sched_barrier(0);
       const int k2 = (kg + 2 < last) ? kg + 2 : last;
       load_a(k2, v0);
-      load_b(k2, b0);
+      load_x(k2, x0);
       __builtin_amdgcn_sched_barrier(0);
-      products(v1, b1, kg + 1);
+      stage(1, x1, b);
+      products(v1, b, kg + 1);
       __builtin_amdgcn_sched_barrier(0);
       const int k3 = (kg + 3 < last) ? kg + 3 : last;
       load_a(k3, v1);
-      load_b(k3, b1);
+      load_x(k3, x1);
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (kg < nfull) products(v0, b0, kg);
+    if (kg < nfull) {
+      stage(0, x0, b);
+      products(v0, b, kg);
+    }
   }
   if ((nfull << 6) < n) {
     // ragged last group: columns past n read as 0 (zero padding of the copy, zero X rows)
