@@ -154,8 +154,8 @@ KERNEL_SYMBOLS = {  # profile marker name -> (regex on the kernel symbol, source
     "atq_bf16c": (r"k_atq_bf16c<", ["gemm_mixed.hip"]),
     "ax_final": (r"k_ax_bf16<\d+, \d+, 3[,>]", ["gemm_mixed.hip"]),
     "atq_final": (r"k_atq_bf16<\d+, 3[,>]", ["gemm_mixed.hip"]),
-    "gemm_ax_f64": (r"k_gemm_ax_f64<\d+, \d+, float>", ["gemm.hip"]),
-    "gemm_atq_f64": (r"k_gemm_atq_f64<\d+, float>", ["gemm.hip"]),
+    "gemm_ax_f64": (r"k_gemm_ax_f64<\d+, \d+, float[,>]", ["gemm.hip"]),
+    "gemm_atq_f64": (r"k_gemm_atq_f64<\d+, float[,>]", ["gemm.hip"]),
 }
 CALIB_BYTES = 1 << 30
 
