@@ -253,8 +253,13 @@ def summarize_trace(d, command):
     other_ms, other_calls = 0.0, 0
     for r in rows:
         name = r["Name"]
-        name = name[:name.index("(", 1)] if name.startswith("(anonymous") else name.split("(")[0]
-        if "tsv::" not in name and not name.startswith("(anonymous namespace)::k_"):
+        anon = "(anonymous namespace)::k_"
+        if anon in name:  # the library's file-local kernels
+            i = name.index(anon)
+            name = name[:i] + anon + name[i + len(anon):].split("(")[0]
+        else:
+            name = name.split("(")[0]
+        if "tsv::" not in name and anon not in name:
             other_ms += float(r["TotalDurationNs"]) / 1e6
             other_calls += int(r["Calls"])
             continue

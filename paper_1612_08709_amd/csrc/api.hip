@@ -176,6 +176,91 @@ __global__ __launch_bounds__(RINV_THREADS) void k_rinv_gate(const double* __rest
       T[idx] = (idx / l == idx % l) ? 1.0 : 0.0;
 }
 
+// The same two steps for l <= LM <= 64 in one wave, with no barrier: lane j owns column j.
+// Cholesky (right-looking): at step k the pivot G_kk and the row R_k. = G_k. / sqrt(G_kk)
+// come from lane k and from each lane, and G_ij -= R_ki R_kj updates lane j's column, the
+// scalar R_ki read from lane i.  A lane keeps only the entries i <= j of its column
+// meaningful; the rest take junk that is never read.  R goes to LDS transposed, and
+// T = R^-1 follows by the column sweep of back substitution on the identity (lane j solves
+// R t = e_j: t_p = b_p / R_pp, then b_i -= R_ip t_p for i < p), each R_ip a broadcast LDS
+// read.  The gate is the one of k_rinv_gate; *chol_bad records a failed pivot.
+__device__ __forceinline__ double lane_bcast(double x, int lane) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int LM>
+__global__ __launch_bounds__(64) void k_chol_rinv_gate(const double* __restrict__ G, int l,
+                                                       double kappa_max,
+                                                       double* __restrict__ T,
+                                                       int* __restrict__ use_q,
+                                                       int* __restrict__ chol_bad) {
+  __shared__ double Rt[LM * LM];  // Rt[p * LM + i] = R_ip
+  const int j = threadIdx.x;
+  double g[LM];
+#pragma unroll
+  for (int i = 0; i < LM; ++i) g[i] = (j < l && i <= j) ? G[i * l + j] : 0.0;
+  int fail = 0;
+#pragma unroll
+  for (int k = 0; k < LM; ++k) {
+    if (k < l && !fail) {  // uniform
+      const double piv = lane_bcast(g[k], k);
+      if (!(piv > 0.0) || !isfinite(piv)) {
+        fail = 1;
+      } else {
+        g[k] *= 1.0 / sqrt(piv);  // lane j >= k: R_kj
+#pragma unroll
+        for (int i = k + 1; i < LM; ++i) g[i] = fma(-lane_bcast(g[k], i), g[k], g[i]);
+      }
+    }
+  }
+  double rn = 0.0;
+#pragma unroll
+  for (int i = 0; i < LM; ++i) {
+    const double r = (i <= j && j < l) ? g[i] : 0.0;
+    Rt[j * LM + i] = r;
+    rn = fma(r, r, rn);
+  }
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // the wave's LDS writes are done (lgkmcnt 0)
+  __builtin_amdgcn_wave_barrier();
+  double b[LM];
+#pragma unroll
+  for (int i = 0; i < LM; ++i) b[i] = (i == j) ? 1.0 : 0.0;
+  if (!fail) {
+#pragma unroll
+    for (int p = LM - 1; p >= 0; --p) {
+      if (p < l) {
+        const double t = b[p] / Rt[p * LM + p];
+        b[p] = t;
+#pragma unroll
+        for (int i = 0; i < p; ++i) b[i] = fma(-Rt[p * LM + i], t, b[i]);
+      }
+    }
+  }
+  double tn = 0.0;
+#pragma unroll
+  for (int i = 0; i < LM; ++i) tn = fma(b[i], b[i], tn);
+  if (j >= l) tn = 0.0;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    rn += __shfl_xor(rn, off);
+    tn += __shfl_xor(tn, off);
+  }
+  const double kap = sqrt(rn) * sqrt(tn);
+  const int bad = fail || !(kap <= kappa_max);  // also catches NaN / Inf
+  if (j < l) {
+#pragma unroll
+    for (int i = 0; i < LM; ++i)
+      if (i < l) T[i * l + j] = bad ? (i == j ? 1.0 : 0.0) : b[i];
+  }
+  if (j == 0) {
+    *use_q = bad;
+    *chol_bad = fail;
+  }
+}
+
 // T = R diag(S) (n x n), for the second orthonormalization of U = Q2 R2.
 __global__ void k_scale_cols(const double* __restrict__ R, const double* __restrict__ S, int n,
                              double* __restrict__ T, const int* __restrict__ gate) {
@@ -434,10 +519,21 @@ hipError_t basis_via_r(const TsqrPlan& p, double* Y, int64_t rows, int l, const 
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), (size_t)l * l * sizeof(double), s, G, l, Rc,
-                     chol_bad);
-  hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), (size_t)l * l * sizeof(double),
-                     s, Rc, l, kKappaMax, T, use_q, chol_bad);
+  if (l <= 16) {
+    hipLaunchKernelGGL(k_chol_rinv_gate<16>, dim3(1), dim3(64), 0, s, G, l, kKappaMax, T, use_q,
+                       chol_bad);
+  } else if (l <= 32) {
+    hipLaunchKernelGGL(k_chol_rinv_gate<32>, dim3(1), dim3(64), 0, s, G, l, kKappaMax, T, use_q,
+                       chol_bad);
+  } else if (l <= 64) {
+    hipLaunchKernelGGL(k_chol_rinv_gate<64>, dim3(1), dim3(64), 0, s, G, l, kKappaMax, T, use_q,
+                       chol_bad);
+  } else {
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), (size_t)l * l * sizeof(double), s, G, l, Rc,
+                       chol_bad);
+    hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), (size_t)l * l * sizeof(double),
+                       s, Rc, l, kKappaMax, T, use_q, chol_bad);
+  }
   TsqrPlan pq = p;
   pq.gate = use_q;
   e = tsqr_factor(pq, Y, TSSVD_F64, l, s);
