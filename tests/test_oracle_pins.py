@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 from oracle import checks, grad_ref, philox
+from oracle.gram_ref import alg3, alg4, gram_svd_ref, lowrank_gram_ref
 from oracle.lowrank_ref import lowrank_ref
 from oracle.tssvd_ref import discard_rule, tssvd_ref, tsqr_ref
 from synth import matrices as sm
@@ -140,6 +141,114 @@ def test_alg7_reproduces_printed_error(l):
         r = int(np.count_nonzero(s))
         assert checks.maxentry_ortho(U, r) < 10 * g["mu"]
         assert checks.maxentry_ortho(V, r) < 10 * g["mv"]
+
+
+# ---------------------------------------------------------------- Gram-based SVD (Alg. 3/4/8)
+
+@pytest.mark.parametrize("shape,seed", [((9, 4), 11), ((40, 6), 13)])
+@pytest.mark.parametrize("double", [False, True])
+def test_gram_svd_matches_50_digit_svd(shape, seed, double):
+    """Brute force: mpmath SVD at 50 digits.  Well-conditioned inputs, where squaring the
+    condition number in the Gram matrix still leaves ~1e-12 accuracy."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal(shape) * rng.uniform(0.5, 2.0, size=shape[1])
+    U, s, V, r = gram_svd_ref(A, double=double)
+    mpmath.mp.dps = 50
+    Um, Sm, Vm = mpmath.svd_r(mpmath.matrix(A.tolist()), full_matrices=False)
+    sm_ = np.array([float(Sm[i]) for i in range(shape[1])])
+    Um_ = np.array(Um.tolist(), dtype=float)
+    Vm_ = np.array(Vm.tolist(), dtype=float).T
+    order = np.argsort(-sm_)
+    sm_, Um_, Vm_ = sm_[order], Um_[:, order], Vm_[:, order]
+    assert r == shape[1]
+    np.testing.assert_allclose(s, sm_, rtol=1e-12, atol=0)
+    for j in range(shape[1]):
+        assert _subspace_cos(U[:, j], Um_[:, j]) > 1 - 1e-11
+        assert _subspace_cos(V[:, j], Vm_[:, j]) > 1 - 1e-11
+    np.testing.assert_allclose((U * s) @ V.T, A, atol=1e-12 * np.abs(A).max())
+
+
+def test_gram_discard_at_sqrt_wp():
+    """Alg. 3/4 drop singular values below sqrt(wp) max(sigma) (not wp as in Alg. 1/2):
+    with wp = 1e-11 the cut is 3.16e-6, so of sigma = 10^0 .. 10^-9 in steps of 10^-1
+    exactly the six values >= 1e-5 remain, recovered to the Gram method's accuracy."""
+    sigma = 10.0 ** -np.arange(10)
+    A = sm.planted(3000, 10, sigma, workload=96)
+    for double in (False, True):
+        U, s, V, r = gram_svd_ref(A, wp=1e-11, double=double)
+        assert r == 6
+        assert np.max(np.abs(s[:6] - sigma[:6]) / sigma[:6]) < 1e-6
+        assert np.all(s[6:] == 0) and np.all(U[:, 6:] == 0)
+
+
+def test_gram_second_pass_restores_orthonormality():
+    """Section 2: the Gram route loses orthonormality like eps kappa^2, and running it twice
+    (Alg. 4) restores it.  kappa = 1e5 here: Alg. 3's U^T U misses I by ~eps 1e10, Alg. 4's
+    by ~eps, and both keep the planted values."""
+    sigma = np.logspace(0, -5, 8)
+    A = sm.planted(4000, 8, sigma, workload=97)
+    U3, s3, _, r3 = gram_svd_ref(A, double=False)
+    U4, s4, _, r4 = gram_svd_ref(A, double=True)
+    assert r3 == r4 == 8
+    assert checks.ortho_spec(U3) > 1e-9
+    assert checks.ortho_spec(U4) < 1e-14
+    np.testing.assert_allclose(s4, sigma, rtol=1e-5)
+
+
+def test_gram_rank_one_closed_form():
+    """A = x y^T: sigma_1 = |x||y| with u_1, v_1 along x, y; the rest is discarded."""
+    rng = np.random.default_rng(8)
+    x, y = rng.standard_normal(300), rng.standard_normal(6)
+    U, s, V, r = gram_svd_ref(np.outer(x, y), wp=1e-11, double=True)
+    assert r == 1
+    assert abs(s[0] - np.linalg.norm(x) * np.linalg.norm(y)) <= 1e-14 * s[0]
+    assert _subspace_cos(U[:, 0], x) > 1 - 1e-14
+    assert _subspace_cos(V[:, 0], y) > 1 - 1e-14
+
+
+def _golden_alg8():
+    rows = []
+    with open(os.path.join(GOLDEN, "paper_alg8_errors.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                t = line.split()
+                rows.append(dict(table=t[0], m=int(t[1]), n=int(t[2]), l=int(t[3]), i=int(t[4]),
+                                 err=float(t[5]), mu=float(t[6]), mv=float(t[7])))
+    return rows
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("l", [20, 10])
+def test_alg8_reproduces_printed_error(l):
+    """Tables tab56* / partialSVDerr: the printed spectral error of Algorithm 8, the first
+    planted sigma below sqrt(wp) = 3.16e-6 (sigma_7 = 10^(-120/19) for l = 20, sigma_4 =
+    10^(-60/9) for l = 10).  m = 10,000, n = 2,000, three independent sketches."""
+    g = [r for r in _golden_alg8() if r["l"] == l][0]
+    m, n, i = 10_000, 2_000, g["i"]
+    A = sm.dct_planted(m, n, sm.paper_spectrum(l))
+    for sub in range(3):
+        Om = sm.gaussian((n, l), 92, "omega", sub)
+        U, s, V = lowrank_gram_ref(A, Om, k=l, q=i, wp=1e-11)
+        err = checks.spectral_residual(A, U, s, V, iters=20)
+        assert abs(err - g["err"]) <= 0.01 * g["err"], (err, g["err"])
+        r = int(np.count_nonzero(s))
+        assert checks.maxentry_ortho(U, r) < 10 * g["mu"]
+        assert checks.maxentry_ortho(V, r) < 10 * g["mv"]
+
+
+def test_alg8_exact_rank_reduces_to_textbook_svd():
+    """rank(A) = l: the Gram route also returns the exact top-k SVD (numpy), q = 0 and 2."""
+    m, n, l, k = 400, 120, 10, 6
+    sigma = 1.0 / np.arange(1, l + 1)
+    A = sm.planted(m, n, sigma, workload=98)
+    Om = sm.sketch(n, l, 98)
+    for q in (0, 2):
+        U, s, V = lowrank_gram_ref(A, Om, k, q)
+        Ue, se, Vhe = np.linalg.svd(A, full_matrices=False)
+        np.testing.assert_allclose(s, se[:k], rtol=1e-12)
+        for j in range(k):
+            assert _subspace_cos(U[:, j], Ue[:, j]) > 1 - 1e-11
+            assert _subspace_cos(V[:, j], Vhe[j]) > 1 - 1e-11
 
 
 def test_lowrank_exact_rank_reduces_to_textbook_svd():
