@@ -95,6 +95,18 @@ typedef struct {
  * copy instead of the float32 A: half the bytes, bit-identical products.  With this flag
  * the workspace is smaller by that amount and every pass reads the float32 A. */
 #define TSSVD_FLAG_NO_A_COPY 2
+/* Gram-based route (Section 2's second method, with the explicit column normalization of
+ * the paper's remark on normalizing).  tssvd: Algorithm 3 when ortho == TSSVD_ORTHO_ONCE,
+ * else Algorithm 4 (always two passes): B = A^* A, eigendecomposition B = V D V^*,
+ * U~ = A V, sigma = column norms of U~, columns with sigma < max(sigma) sqrt(wp) dropped
+ * (wp = working_precision), U = U~ Sigma^-1; Algorithm 4 repeats the pass on U and forms
+ * U, Sigma, V from the SVD of R = T W^* Sigma~ V~^*.  lowrank_svd: Algorithm 8 (Algorithm 5
+ * with its intermediate bases from Algorithm 3 and its last from Algorithm 4, then
+ * Algorithm 6); working_precision > 0 is allowed with this flag.  Triplets past the kept
+ * rank come back as zero columns with sigma = 0 and info->rank reports the rank.  The Gram
+ * matrix squares the condition number: singular values below ~sqrt(eps) sigma_1 are not
+ * resolved (the paper's trade of accuracy for one pass). */
+#define TSSVD_FLAG_GRAM 4
 
 /* Device-side record written (when non-NULL) at the end of every call. */
 typedef struct {

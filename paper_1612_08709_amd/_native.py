@@ -21,6 +21,7 @@ ORTHO_AUTO, ORTHO_ONCE, ORTHO_TWICE = 0, 1, 2
 NUM_NONFINITE, NUM_NO_CONVERGENCE = 1, 2
 FLAG_F32_MFMA_FINAL = 1
 FLAG_NO_A_COPY = 2
+FLAG_GRAM = 4
 
 # every exported symbol declared in include/tssvd.h
 EXPORTS = (

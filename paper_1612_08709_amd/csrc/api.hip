@@ -261,6 +261,135 @@ __global__ __launch_bounds__(64) void k_chol_rinv_gate(const double* __restrict_
   }
 }
 
+// ---------------------------------------------------------------- Gram-based SVD
+// Algorithms 3 and 4 (and the bases of Algorithm 8) share one normalization step: the
+// columns of U~ = Y V get their Euclidean norms explicitly (the paper's remark on
+// normalizing), norms below max(norm) sqrt(wp) are discarded, and the kept columns are
+// divided by their norms.  One workgroup (n <= 256 threads): thread j owns column j.
+//   sumsq  : sum_i U~_ij^2 (input)
+//   nrm    : the kept norms, 0 for a discarded column (output)
+//   scale  : sgn_j / nrm_j, 0 for a discarded column (output)
+//   pos    : with sort != 0, the column's place when the kept norms are sorted descending
+//            (ties by index) and discarded columns follow in index order; else pos_j = j
+//   sgn    : with sign != 0, the sign making w^T v_j >= 0 for V's column j (the output
+//            sign convention); else 1
+//   rank   : number of kept columns (optional; also written to info->rank when given)
+//   out_sig: when given, the kept norms at their sorted places (0 for discarded ones)
+__global__ __launch_bounds__(256) void k_gram_normalize(const double* __restrict__ sumsq, int n,
+                                                        double wp, const double* __restrict__ V,
+                                                        int ldv, int sort, int sign,
+                                                        double* __restrict__ nrm,
+                                                        double* __restrict__ scale,
+                                                        int* __restrict__ pos,
+                                                        int* __restrict__ rank,
+                                                        double* __restrict__ out_sig,
+                                                        tssvd_info* __restrict__ info) {
+  __shared__ double s_n[256];
+  __shared__ int s_keep[256];
+  const int j = threadIdx.x;
+  const double v = (j < n) ? sqrt(sumsq[j]) : 0.0;
+  s_n[j] = v;
+  __syncthreads();
+  double mx = 0.0;
+  for (int i = 0; i < n; ++i) mx = fmax(mx, s_n[i]);  // same order in every thread
+  const double thr = (wp > 0.0) ? mx * sqrt(wp) : 0.0;
+  const int keep = (j < n) && (v > 0.0) && !(v < thr) && isfinite(v);
+  s_keep[j] = keep;
+  __syncthreads();
+  if (j >= n) return;
+  double sg = 1.0;
+  if (sign) {
+    double d = 0.0;
+    for (int i = 0; i < n; ++i) d = fma(sign_ref(i), V[i * ldv + j], d);
+    sg = (d < 0.0) ? -1.0 : 1.0;
+  }
+  int p = j;
+  if (sort) {
+    p = 0;
+    if (keep) {
+      for (int i = 0; i < n; ++i)
+        p += s_keep[i] && (s_n[i] > v || (s_n[i] == v && i < j));
+    } else {
+      for (int i = 0; i < n; ++i) p += s_keep[i] || (!s_keep[i] && i < j);
+    }
+  }
+  nrm[j] = keep ? v : 0.0;
+  scale[j] = keep ? sg / v : 0.0;
+  pos[j] = p;
+  if (out_sig) out_sig[p] = keep ? v : 0.0;
+  if (j == 0 && (rank || info)) {
+    int r = 0;
+    for (int i = 0; i < n; ++i) r += s_keep[i];
+    if (rank) *rank = r;
+    if (info) info->rank = r;
+  }
+}
+
+// Y (rows x n, stride ldy) in place: column j times scale_j, moved to column pos_j.  A
+// workgroup stages GN_ROWS rows in LDS.
+constexpr int GN_ROWS = 8;
+__global__ __launch_bounds__(256) void k_scale_permute_cols(double* __restrict__ Y, int64_t rows,
+                                                            int n, int64_t ldy,
+                                                            const double* __restrict__ scale,
+                                                            const int* __restrict__ pos) {
+  __shared__ double buf[GN_ROWS * TSSVD_N_MAX];
+  const int64_t r0 = (int64_t)blockIdx.x * GN_ROWS;
+  const int cnt = (int)((rows - r0 < GN_ROWS) ? rows - r0 : GN_ROWS);
+  for (int idx = threadIdx.x; idx < cnt * n; idx += 256) {
+    const int r = idx / n, j = idx - r * n;
+    buf[r * n + pos[j]] = Y[(r0 + r) * ldy + j] * scale[j];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < cnt * n; idx += 256) {
+    const int r = idx / n, j = idx - r * n;
+    Y[(r0 + r) * ldy + j] = buf[r * n + j];
+  }
+}
+
+// Small n x n results of the Gram routes (one thread per output entry, fixed order):
+//   mode 0: Out[i][pos_j] = V[i][j] * sgn_j with sgn_j = sign(scale_j), 0 when scale_j = 0
+//           (V of Algorithm 3, sorted and signed)
+//   mode 1: Out[i][j] = V[i][j] * scale_j (T = V diag(1 / norm) of an Algorithm 3 basis)
+__global__ void k_gram_small(const double* __restrict__ V, int n, const double* __restrict__ scale,
+                             const int* __restrict__ pos, int mode, double* __restrict__ Out,
+                             int ldo) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int i = idx / n, j = idx - i * n;
+  const double sc = scale[j];
+  if (mode == 0)
+    Out[i * ldo + pos[j]] = (sc == 0.0) ? 0.0 : ((sc < 0.0) ? -V[i * n + j] : V[i * n + j]);
+  else
+    Out[i * ldo + j] = V[i * n + j] * sc;
+}
+
+// R = T W^T Sigma~ V~^T of Algorithm 4 (n x n): R_ij = t_i sum_k W_ki sigma~_k V~_jk.
+__global__ void k_gram_R(const double* __restrict__ t, const double* __restrict__ W,
+                         const double* __restrict__ sig, const double* __restrict__ Vt, int n,
+                         double* __restrict__ R) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int i = idx / n, j = idx - i * n;
+  double acc = 0.0;
+  for (int k = 0; k < n; ++k) acc = fma(W[k * n + i] * sig[k], Vt[j * n + k], acc);
+  R[idx] = t[i] * acc;
+}
+
+// Entries past the kept rank: sigma_j = 0 and columns j of P and V zeroed (the rank
+// deficient directions of R in Algorithm 4 carry rounding-level singular values).
+__global__ void k_truncate_rank(const int* __restrict__ rank, double* __restrict__ S, double* P,
+                                int ldp, double* V, int ldv, int n, tssvd_info* info) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = *rank;
+  if (idx == 0 && info) info->rank = r;
+  if (idx >= n * n) return;
+  const int i = idx / n, j = idx - i * n;
+  if (j < r) return;
+  if (i == 0) S[j] = 0.0;
+  P[i * ldp + j] = 0.0;
+  V[i * ldv + j] = 0.0;
+}
+
 // T = R diag(S) (n x n), for the second orthonormalization of U = Q2 R2.
 __global__ void k_scale_cols(const double* __restrict__ R, const double* __restrict__ S, int n,
                              double* __restrict__ T, const int* __restrict__ gate) {
@@ -284,7 +413,9 @@ __global__ void k_small_gemm(const double* __restrict__ A, const double* __restr
 struct TssvdWs {
   TsqrPlan p;
   double *Ut, *S, *Vt, *T, *P2, *S2, *W2, *V2, *G, *part, *ortho;
+  double *gnrm, *gnrm2, *gscale;  // Gram route: norms of the two passes, column scales
   int* gate;
+  int* gpos;  // Gram route: column places (n) and the kept rank (one more int)
   size_t bytes;
 };
 
@@ -305,9 +436,68 @@ TssvdWs tssvd_layout(int64_t m, int n, void* work) {
   w.G = c.take<double>(nn);
   w.part = c.take<double>(atq_partials(m, n, n));
   w.ortho = c.take<double>(1);
+  w.gnrm = c.take<double>(n);
+  w.gnrm2 = c.take<double>(n);
+  w.gscale = c.take<double>(n);
   w.gate = c.take<int>(4);
+  w.gpos = c.take<int>((size_t)n + 1);
   w.bytes = c.off + 256;
   return w;
+}
+
+// Algorithm 3 (ortho == ONCE) or Algorithm 4 on A (m x n), every step on the GPU.  The
+// eigendecompositions of the Gram matrices use the one-sided Jacobi kernel: for a symmetric
+// positive semidefinite matrix the SVD is the eigendecomposition, sorted descending.  The
+// m x n scratch is the TSQR plan's reflector storage, which this route does not use.
+hipError_t tssvd_gram(const void* A, int a_dtype, int64_t m, int ni, int64_t lda, double* U,
+                      int64_t ldu, double* S, double* V, int64_t ldv, tssvd_info* info,
+                      TssvdWs& w, const tssvd_opts& o, hipStream_t s) {
+  const int64_t n = ni;
+  const double wp = o.working_precision;
+  const unsigned gs = (unsigned)((ni * ni + 255) / 256);
+  const unsigned gr = (unsigned)((m + GN_ROWS - 1) / GN_ROWS);
+  int* rank = w.gpos + ni;
+  double* scratch = w.p.Vleaf;
+  hipError_t e;
+#define GTRY(x) do { e = (x); if (e != hipSuccess) return e; } while (0)
+  GTRY(gram_any(A, a_dtype, lda, m, ni, w.G, ni, w.part, s));                 // B = A^* A
+  GTRY(jacobi_svd(w.G, ni, ni, 0, 0.0, o.max_jacobi_sweeps, 0, w.Ut, w.S, w.Vt, info, s));
+  GTRY(gemm_ax_f64(A, a_dtype, lda, m, n, w.Vt, ni, ni, U, (int)ldu, s));    // U~ = A V
+  GTRY(column_sumsq(U, TSSVD_F64, m, ni, ldu, w.S2, w.part, s));
+  if (o.ortho == TSSVD_ORTHO_ONCE) {
+    // Algorithm 3: U = U~ Sigma^-1, sorted by sigma, output sign convention
+    hipLaunchKernelGGL(k_gram_normalize, dim3(1), dim3(256), 0, s, w.S2, ni, wp, w.Vt, ni, 1,
+                       1, w.gnrm, w.gscale, w.gpos, rank, S, info);
+    hipLaunchKernelGGL(k_scale_permute_cols, dim3(gr), dim3(256), 0, s, U, m, ni, ldu,
+                       w.gscale, w.gpos);
+    hipLaunchKernelGGL(k_gram_small, dim3(gs), dim3(256), 0, s, w.Vt, ni, w.gscale, w.gpos, 0,
+                       V, (int)ldv);
+    return hipGetLastError();
+  }
+  // Algorithm 4: Y = U~ Sigma~^-1 (in U), Z = Y^* Y = W D W^*, Q~ = Y W, T = norms of Q~,
+  // Q = Q~ T^-1, R = T W^* Sigma~ V~^*, R = P Sigma V^*, U = Q P.
+  hipLaunchKernelGGL(k_gram_normalize, dim3(1), dim3(256), 0, s, w.S2, ni, wp, w.Vt, ni, 0, 0,
+                     w.gnrm, w.gscale, w.gpos, rank, nullptr, nullptr);
+  hipLaunchKernelGGL(k_scale_permute_cols, dim3(gr), dim3(256), 0, s, U, m, ni, ldu, w.gscale,
+                     w.gpos);
+  GTRY(gram_any(U, TSSVD_F64, ldu, m, ni, w.G, ni, w.part, s));               // Z = Y^* Y
+  GTRY(jacobi_svd(w.G, ni, ni, 0, 0.0, o.max_jacobi_sweeps, 0, w.P2, w.S, w.W2, info, s));
+  GTRY(gemm_ax_f64(U, TSSVD_F64, ldu, m, n, w.W2, ni, ni, scratch, ni, s));   // Q~ = Y W
+  GTRY(column_sumsq(scratch, TSSVD_F64, m, ni, ni, w.S2, w.part, s));
+  hipLaunchKernelGGL(k_gram_normalize, dim3(1), dim3(256), 0, s, w.S2, ni, wp, w.W2, ni, 0, 0,
+                     w.gnrm2, w.gscale, w.gpos, rank, nullptr, nullptr);
+  hipLaunchKernelGGL(k_scale_permute_cols, dim3(gr), dim3(256), 0, s, scratch, m, ni,
+                     (int64_t)ni, w.gscale, w.gpos);                            // Q
+  hipLaunchKernelGGL(k_gram_R, dim3(gs), dim3(256), 0, s, w.gnrm2, w.W2, w.gnrm, w.Vt, ni,
+                     w.T);
+  GTRY(jacobi_svd(w.T, ni, ni, 0, 0.0, o.max_jacobi_sweeps, 1, w.P2, w.S2, w.V2, info, s));
+  hipLaunchKernelGGL(k_truncate_rank, dim3(gs), dim3(256), 0, s, rank, w.S2, w.P2, ni, w.V2,
+                     ni, ni, info);
+  GTRY(gemm_ax_f64(scratch, TSSVD_F64, ni, m, n, w.P2, ni, ni, U, (int)ldu, s));  // U = Q P
+  GTRY(copy_matrix(w.S2, 1, ni, ni, S, ni, s));
+  GTRY(copy_matrix(w.V2, n, ni, ni, V, ldv, s));
+#undef GTRY
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -398,6 +588,8 @@ int tssvd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, dou
   hipStream_t s = (hipStream_t)stream;
 
   TRY(info_init(info, s));
+  if (o.flags & TSSVD_FLAG_GRAM)
+    return hip_status(tssvd_gram(A, a_dtype, m, ni, lda, U, ldu, S, V, ldv, info, w, o, s));
   // Algorithm 1: TSQR A = Q R; SVD R = U~ S V~^T (discard rule inside); U = Q U~.
   TRY(tsqr_factor(w.p, A, a_dtype, lda, s, true));
   TRY(jacobi_svd(tsqr_root(w.p), ni, ni, 0, o.working_precision, o.max_jacobi_sweeps, 1, w.Ut,
@@ -440,6 +632,8 @@ namespace {
 struct LowrankWs {
   TsqrPlan pY, pZ;
   double *X, *Y, *Z, *Zraw, *part, *I, *P, *sig, *W, *Wk, *G, *ortho, *Tq, *Rc;
+  double *gsum, *gnrm, *gscale;  // Gram route (Algorithm 8): norms and column scales
+  int* gpos;                     // Gram route: column places (l) and the kept rank
   void* pack;
   void* Acopy;  // bfloat16 copy of A for the mixed power steps (or null)
   int* gate;
@@ -482,6 +676,10 @@ LowrankWs lowrank_layout(int64_t m, int64_t n, int k, int l, void* work, bool mi
   w.Tq = c.take<double>(ll);
   w.Rc = c.take<double>(ll);
   w.ortho = c.take<double>(1);
+  w.gsum = c.take<double>(l);
+  w.gnrm = c.take<double>(l);
+  w.gscale = c.take<double>(l);
+  w.gpos = c.take<int>((size_t)l + 1);
   w.gate = c.take<int>(4);
   w.bytes = c.off + 256;
   return w;
@@ -501,6 +699,31 @@ int lowrank_check(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t 
 // kappa(Y)^2 eps, harmless for an intermediate step as long as kappa is moderate, so when
 // the Cholesky factorization fails or ||R||_F ||R^-1||_F > 1e4 the device gate falls back to
 // the TSQR of Y with the explicit Householder Q written over Y and T = I.
+// Algorithm 3 on Y (rows x l, FP64, stride l) as an l x l map: T = V diag(1 / norm_j), so
+// that Y T = (Y V) diag(1 / norm) is Algorithm 3's normalized left factor.  The Gram matrix
+// Y^* Y is eigendecomposed by the one-sided Jacobi kernel (its SVD, for a positive
+// semidefinite matrix), Y V is formed in `scratch` (rows x l) for the explicit column norms,
+// and norms below max(norm) sqrt(wp) give zero columns of T.  l x l buffers: G, E (the
+// eigenvectors), Ud and sd (unused Jacobi outputs).
+hipError_t gram_basis(const double* Y, int64_t rows, int l, double wp, int sweeps, double* G,
+                      double* E, double* Ud, double* sd, double* scratch, double* sumsq,
+                      double* nrm, double* scale, int* pos, int* rank, double* T, double* part,
+                      tssvd_info* info, hipStream_t s) {
+  hipError_t e = gram_any(Y, TSSVD_F64, l, rows, l, G, l, part, s);            // Y^* Y
+  if (e != hipSuccess) return e;
+  e = jacobi_svd(G, l, l, 0, 0.0, sweeps, 0, Ud, sd, E, info, s);              // = V D V^*
+  if (e != hipSuccess) return e;
+  e = gemm_ax_f64(Y, TSSVD_F64, l, rows, l, E, l, l, scratch, l, s);           // Y V
+  if (e != hipSuccess) return e;
+  e = column_sumsq(scratch, TSSVD_F64, rows, l, l, sumsq, part, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gram_normalize, dim3(1), dim3(256), 0, s, sumsq, l, wp, E, l, 0, 0, nrm,
+                     scale, pos, rank, nullptr, nullptr);
+  hipLaunchKernelGGL(k_gram_small, dim3((l * l + 255) / 256), dim3(256), 0, s, E, l, scale, pos,
+                     1, T, l);
+  return hipGetLastError();
+}
+
 constexpr double kKappaMax = 1e4;
 hipError_t basis_via_r(const TsqrPlan& p, double* Y, int64_t rows, int l, const double* I,
                        double* T, double* G, double* Rc, double* part, int* flags,
@@ -573,7 +796,8 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   if (check_opts(o) != TSSVD_OK) return TSSVD_E_INVALID_ARG;
   const bool mixed = o.prec == TSSVD_PREC_MIXED;
   if (mixed && a_dtype != TSSVD_F32) return TSSVD_E_INVALID_ARG;
-  if (o.working_precision > 0.0) return TSSVD_E_UNSUPPORTED;
+  const bool gram = (o.flags & TSSVD_FLAG_GRAM) != 0;
+  if (o.working_precision > 0.0 && !gram) return TSSVD_E_UNSUPPORTED;
   const int ki = (int)k, li = (int)l;
   const bool acopy = mixed && q >= 1 && !(o.flags & TSSVD_FLAG_NO_A_COPY);
   LowrankWs w = lowrank_layout(m, n, ki, li, work, mixed, acopy);
@@ -626,10 +850,18 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   // the product uses Y itself, A^* Q_j = (A^* Y) R_j^-1; in mixed precision Q_j is formed
   // first (in FP64, written straight out as bfloat16 operand fragments), because
   // bfloat16 rounding of Y's entries would be amplified by R_j^-1.
+  // Algorithm 8 (TSSVD_FLAG_GRAM): the same loop with T from Algorithm 3 instead.
   int* use_q = w.gate + 1;
+  int* grank = w.gpos + li;
+  auto basis = [&](const TsqrPlan& p, double* Yb, int64_t rows) -> hipError_t {
+    if (!gram) return basis_via_r(p, Yb, rows, li, w.I, w.Tq, w.G, w.Rc, w.part, use_q, s);
+    return gram_basis(Yb, rows, li, o.working_precision, o.max_jacobi_sweeps, w.G, w.W, w.P,
+                      w.sig, p.Vleaf, w.gsum, w.gnrm, w.gscale, w.gpos, grank, w.Tq, w.part,
+                      info, s);
+  };
   TRY(ax(w.X, q == 0));                                                        // A Q~_0
   for (int64_t j = 0; j < q; ++j) {
-    TRY(basis_via_r(w.pY, w.Y, m, li, w.I, w.Tq, w.G, w.Rc, w.part, use_q, s));  // Q_j = Y T
+    TRY(basis(w.pY, w.Y, m));                                                  // Q_j = Y T
     if (mixed) {
       TRY(gemm_ax_f64_pack_bf16(w.Y, l, m, w.Tq, li, li, w.pack, s));         // Q_j, packed
       TRY(atq(nullptr, false, w.Z));                                           // A^* Q_j
@@ -637,12 +869,23 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
       TRY(atq(w.Y, false, w.Zraw));                                            // A^* Y
       TRY(gemm_ax_f64(w.Zraw, TSSVD_F64, l, n, l, w.Tq, li, li, w.Z, li, s)); // A^* Q_j
     }
-    TRY(basis_via_r(w.pZ, w.Z, n, li, w.I, w.Tq, w.G, w.Rc, w.part, use_q, s));  // Q~_j = Z T
+    TRY(basis(w.pZ, w.Z, n));                                                  // Q~_j = Z T
     TRY(gemm_ax_f64(w.Z, TSSVD_F64, l, n, l, w.Tq, li, li, w.X, li, s));
     TRY(ax(w.X, j == q - 1));                                                  // A Q~_j
   }
-  TRY(orth_inplace(w.pY, w.Y, li, w.I, s));                                    // Q
-  if (o.ortho != TSSVD_ORTHO_ONCE) {
+  if (gram) {
+    // Algorithm 4 on the last Y: Y1 = Y T1 (Algorithm 3), then Q = Y1 T2 (Algorithm 3 on Y1);
+    // the kept rank of the second pass bounds the rank of the result
+    double* Y1 = w.pY.Vleaf;
+    TRY(basis(w.pY, w.Y, m));
+    TRY(gemm_ax_f64(w.Y, TSSVD_F64, l, m, l, w.Tq, li, li, Y1, li, s));
+    TRY(gram_basis(Y1, m, li, o.working_precision, o.max_jacobi_sweeps, w.G, w.W, w.P, w.sig,
+                   w.Y, w.gsum, w.gnrm, w.gscale, w.gpos, grank, w.Tq, w.part, info, s));
+    TRY(gemm_ax_f64(Y1, TSSVD_F64, l, m, l, w.Tq, li, li, w.Y, li, s));      // Q
+  } else {
+    TRY(orth_inplace(w.pY, w.Y, li, w.I, s));                                  // Q
+  }
+  if (!gram && o.ortho != TSSVD_ORTHO_ONCE) {
     // last step orthonormalized twice (Algorithm 2 form), gated like tssvd
     TRY(gemm_atq_f64(w.Y, TSSVD_F64, l, m, l, w.Y, li, li, w.G, li, w.part, s));
     hipLaunchKernelGGL(k_ortho_gate, dim3(1), dim3(256), 0, s, w.G, li, o.ortho, o.reorth_tol,
@@ -658,6 +901,9 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   TRY(tsqr_factor(w.pZ, w.Z, TSSVD_F64, l, s));
   TRY(jacobi_svd(tsqr_root(w.pZ), li, li, 1, 0.0, o.max_jacobi_sweeps, 0, w.P, w.sig, w.W,
                  info, s));
+  if (gram)  // directions dropped by the discard carry rounding-level singular values
+    hipLaunchKernelGGL(k_truncate_rank, dim3((li * li + 255) / 256), dim3(256), 0, s, grank,
+                       w.sig, w.P, li, w.W, li, li, info);
   TRY(copy_matrix(w.W, l, ki, l, w.Wk, k, s));
   TRY(tsqr_apply(w.pZ, w.Wk, ki, V, ldv, s));
   TRY(sign_fix_cols(V, n, (int)ldv, ki, w.P, li, li, s));

@@ -226,10 +226,10 @@ hipError_t gemm_ax_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int64
 // The contraction runs over rows: in one MFMA, k-slot g is row r + g.
 constexpr int ATQ_COLS = 256;
 
-template <int NT, typename TA, bool RS>
+template <int NT, typename TA, bool RS, typename TQ = double>
 __global__ __launch_bounds__(256) void k_gemm_atq_f64(const TA* __restrict__ A, int64_t lda,
                                                       int64_t m, int n,
-                                                      const double* __restrict__ Q, int ldq,
+                                                      const TQ* __restrict__ Q, int ldq,
                                                       int l, int ncol, int nchunk,
                                                       int64_t chunk_rows,
                                                       double* __restrict__ part) {
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) void k_gemm_atq_f64(const TA* __restrict__ A, 
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int col = 16 * nt + li;
-      q[nt] = (rok && col < l) ? Q[rr * ldq + col] : 0.0;
+      q[nt] = (rok && col < l) ? (double)Q[rr * ldq + col] : 0.0;
     }
   };
   double a[4], q[NT];
@@ -352,8 +352,8 @@ size_t atq_partials(int64_t m, int64_t n, int l) {
   return (size_t)nchunk * n * l;
 }
 
-template <int NT, typename TA>
-static void launch_atq(const TA* A, int64_t lda, int64_t m, int64_t n, const double* Q, int ldq,
+template <int NT, typename TA, typename TQ = double>
+static void launch_atq(const TA* A, int64_t lda, int64_t m, int64_t n, const TQ* Q, int ldq,
                        int l, double* part, hipStream_t s) {
   int ncol, nchunk;
   int64_t cr;
@@ -361,24 +361,24 @@ static void launch_atq(const TA* A, int64_t lda, int64_t m, int64_t n, const dou
   const int total = n <= 64 ? (nchunk + 3) / 4 : ncol * nchunk;
   const int grid = ((total + 7) / 8) * 8;
   if (n <= 64)
-    hipLaunchKernelGGL((k_gemm_atq_f64<NT, TA, true>), dim3(grid), dim3(256), 0, s, A, lda, m,
+    hipLaunchKernelGGL((k_gemm_atq_f64<NT, TA, true, TQ>), dim3(grid), dim3(256), 0, s, A, lda, m,
                        (int)n, Q, ldq, l, ncol, nchunk, cr, part);
   else
-    hipLaunchKernelGGL((k_gemm_atq_f64<NT, TA, false>), dim3(grid), dim3(256), 0, s, A, lda, m,
+    hipLaunchKernelGGL((k_gemm_atq_f64<NT, TA, false, TQ>), dim3(grid), dim3(256), 0, s, A, lda, m,
                        (int)n, Q, ldq, l, ncol, nchunk, cr, part);
 }
 
-template <typename TA>
-static hipError_t atq_dispatch(const TA* A, int64_t lda, int64_t m, int64_t n, const double* Q,
+template <typename TA, typename TQ = double>
+static hipError_t atq_dispatch(const TA* A, int64_t lda, int64_t m, int64_t n, const TQ* Q,
                                int ldq, int l, double* part, hipStream_t s) {
   switch ((l + 15) / 16) {
-    case 1: launch_atq<1>(A, lda, m, n, Q, ldq, l, part, s); break;
-    case 2: launch_atq<2>(A, lda, m, n, Q, ldq, l, part, s); break;
-    case 3: launch_atq<3>(A, lda, m, n, Q, ldq, l, part, s); break;
-    case 4: launch_atq<4>(A, lda, m, n, Q, ldq, l, part, s); break;
-    case 5: launch_atq<5>(A, lda, m, n, Q, ldq, l, part, s); break;
-    case 6: launch_atq<6>(A, lda, m, n, Q, ldq, l, part, s); break;
-    case 7: launch_atq<7>(A, lda, m, n, Q, ldq, l, part, s); break;
+    case 1: launch_atq<1, TA, TQ>(A, lda, m, n, Q, ldq, l, part, s); break;
+    case 2: launch_atq<2, TA, TQ>(A, lda, m, n, Q, ldq, l, part, s); break;
+    case 3: launch_atq<3, TA, TQ>(A, lda, m, n, Q, ldq, l, part, s); break;
+    case 4: launch_atq<4, TA, TQ>(A, lda, m, n, Q, ldq, l, part, s); break;
+    case 5: launch_atq<5, TA, TQ>(A, lda, m, n, Q, ldq, l, part, s); break;
+    case 6: launch_atq<6, TA, TQ>(A, lda, m, n, Q, ldq, l, part, s); break;
+    case 7: launch_atq<7, TA, TQ>(A, lda, m, n, Q, ldq, l, part, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -397,8 +397,8 @@ static hipError_t atq_dispatch(const TA* A, int64_t lda, int64_t m, int64_t n, c
 constexpr int GRAM_WG_MAX = 512;
 constexpr int GRAM_DEPTH = 4;  // four-row groups in flight per wave
 
-template <int NT>
-__global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ Y, int64_t rows,
+template <int NT, typename TY = double>
+__global__ __launch_bounds__(256) void k_gram_f64(const TY* __restrict__ Y, int64_t rows,
                                                   int l, int ldy, int64_t chunk,
                                                   double* __restrict__ part) {
   constexpr int NTILE = NT * (NT + 1) / 2;
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ Y, 
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int col = 16 * t + li;
-      y[t] = (ok && col < l) ? Y[row * ldy + col] : 0.0;
+      y[t] = (ok && col < l) ? (double)Y[row * ldy + col] : 0.0;
     }
   };
   const int64_t ngrp = (r1 - r0 + 3) / 4;  // four-row groups of the chunk (r1 > r0)
@@ -480,20 +480,95 @@ static int gram_grid(int64_t rows, int64_t& chunk) {
   return (int)((rows + chunk - 1) / chunk);
 }
 
-static hipError_t gram_f64(const double* Y, int64_t rows, int l, int ldy, double* G, int ldg,
+template <typename TY>
+static hipError_t gram_f64(const TY* Y, int64_t rows, int l, int ldy, double* G, int ldg,
                            double* part, hipStream_t s) {
   int64_t chunk;
   const int nwg = gram_grid(rows, chunk);
   switch ((l + 15) / 16) {
-    case 1: hipLaunchKernelGGL((k_gram_f64<1>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
-    case 2: hipLaunchKernelGGL((k_gram_f64<2>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
-    case 3: hipLaunchKernelGGL((k_gram_f64<3>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
-    case 4: hipLaunchKernelGGL((k_gram_f64<4>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
+    case 1: hipLaunchKernelGGL((k_gram_f64<1, TY>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
+    case 2: hipLaunchKernelGGL((k_gram_f64<2, TY>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
+    case 3: hipLaunchKernelGGL((k_gram_f64<3, TY>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
+    case 4: hipLaunchKernelGGL((k_gram_f64<4, TY>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return reduce_chunks(part, nwg, l, l, G, ldg, s);
+}
+
+// ---------------------------------------------------------------- column sums of squares
+// out[j] = sum_i Y[i][j]^2 (Y rows x l, stride ldy, l <= 256): workgroup c sums rows
+// [c*chunk, (c+1)*chunk) in order, thread j its column (consecutive threads read
+// consecutive columns of a row), and the chunks are added in a fixed order.
+template <typename TY>
+__global__ __launch_bounds__(256) void k_colsq(const TY* __restrict__ Y, int64_t rows, int l,
+                                               int64_t ldy, int64_t chunk,
+                                               double* __restrict__ part) {
+  const int j = threadIdx.x;
+  if (j >= l) return;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = (r0 + chunk < rows) ? r0 + chunk : rows;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // four interleaved running sums, added in order
+  int64_t r = r0;
+  for (; r + 4 <= r1; r += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double y = (double)Y[(r + u) * ldy + j];
+      acc[u] = fma(y, y, acc[u]);
+    }
+  }
+  for (; r < r1; ++r) {
+    const double y = (double)Y[r * ldy + j];
+    acc[0] = fma(y, y, acc[0]);
+  }
+  part[(int64_t)blockIdx.x * l + j] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+hipError_t column_sumsq(const void* Y, int y_dtype, int64_t rows, int l, int64_t ldy, double* out,
+                        double* part, hipStream_t s) {
+  if (l < 1 || l > 256) return hipErrorInvalidValue;
+  int64_t want = (rows + 255) / 256;
+  if (want > GRAM_WG_MAX) want = GRAM_WG_MAX;
+  if (want < 1) want = 1;
+  const int64_t chunk = (rows + want - 1) / want;
+  const int nwg = (int)((rows + chunk - 1) / chunk);
+  if (y_dtype == TSSVD_F64)
+    hipLaunchKernelGGL((k_colsq<double>), dim3(nwg), dim3(256), 0, s, (const double*)Y, rows, l,
+                       ldy, chunk, part);
+  else
+    hipLaunchKernelGGL((k_colsq<float>), dim3(nwg), dim3(256), 0, s, (const float*)Y, rows, l,
+                       ldy, chunk, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return reduce_chunks(part, nwg, 1, l, out, l, s);
+}
+
+size_t column_sumsq_partials(int64_t rows, int l) {
+  int64_t want = (rows + 255) / 256;
+  if (want > GRAM_WG_MAX) want = GRAM_WG_MAX;
+  if (want < 1) want = 1;
+  return (size_t)want * l;
+}
+
+// G = Y^T Y (l x l) for a tall Y of either storage type: the Gram kernel for l <= 64, the
+// split-K A^T Q kernel with Q = Y otherwise.  `part` holds atq_partials(rows, l, l) doubles.
+hipError_t gram_any(const void* Y, int y_dtype, int64_t ldy, int64_t rows, int l, double* G,
+                    int ldg, double* part, hipStream_t s) {
+  if (l <= 64)
+    return (y_dtype == TSSVD_F64)
+               ? gram_f64((const double*)Y, rows, l, (int)ldy, G, ldg, part, s)
+               : gram_f64((const float*)Y, rows, l, (int)ldy, G, ldg, part, s);
+  hipError_t e = (y_dtype == TSSVD_F64)
+                     ? atq_dispatch((const double*)Y, ldy, rows, l, (const double*)Y, (int)ldy,
+                                    l, part, s)
+                     : atq_dispatch((const float*)Y, ldy, rows, l, (const float*)Y, (int)ldy, l,
+                                    part, s);
+  if (e != hipSuccess) return e;
+  int ncol, nchunk;
+  int64_t cr;
+  atq_grid(rows, l, ncol, nchunk, cr);
+  return reduce_chunks(part, nchunk, l, l, G, ldg, s);
 }
 
 hipError_t gemm_atq_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int64_t n,

@@ -86,6 +86,14 @@ hipError_t gemm_atq_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int6
 // pack_operand(Q, m, l, l, MIX_BF16, P) produces (bitwise the same), Q never stored.
 hipError_t gemm_ax_f64_pack_bf16(const double* Y, int64_t ldy, int64_t m, const double* T,
                                  int ldt, int l, void* P, hipStream_t s);
+// G = Y^T Y (l x l, FP64) of a tall Y stored as float64 or float32 (y_dtype); `part` holds
+// atq_partials(rows, l, l) doubles.  Fixed summation order.
+hipError_t gram_any(const void* Y, int y_dtype, int64_t ldy, int64_t rows, int l, double* G,
+                    int ldg, double* part, hipStream_t s);
+// out[j] = sum_i Y[i][j]^2 for a tall Y (l <= 256); `part` holds column_sumsq_partials doubles.
+hipError_t column_sumsq(const void* Y, int y_dtype, int64_t rows, int l, int64_t ldy, double* out,
+                        double* part, hipStream_t s);
+size_t column_sumsq_partials(int64_t rows, int l);
 hipError_t reduce_chunks(const double* part, int nchunk, int64_t n, int l, double* Z, int ldz,
                          hipStream_t s);
 
