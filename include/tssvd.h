@@ -165,6 +165,11 @@ int tssvd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
  *           (seed mod 2^32, seed div 2^32), Box-Muller on (u0,u1), (u2,u3) with
  *           u = (x + 1/2) 2^-32).
  *   U : m x k float64 (ldu), S : k float64, V : n x k float64 (ldv)     (written)
+ * opts->working_precision > 0 is the paper's rank-deficient mode: every basis of Algorithm
+ * 5 is the TSQR's Householder Q with the columns whose |R_jj| < wp |R_11| dropped (set to
+ * zero), and the last basis is orthonormalized twice with the rule applied after each pass.
+ * Triplets past the kept rank come back as zero columns with S = 0; info->rank is the rank.
+ * With TSSVD_FLAG_GRAM the call runs Algorithm 8 instead (see the flag).
  * ------------------------------------------------------------------------------------- */
 int lowrank_svd_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t l, int64_t q,
                                 int32_t a_dtype, const tssvd_opts* opts, size_t* bytes);
@@ -185,7 +190,8 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
  * l, q and options; they are not read.  2q+2 passes over A recompute the forward, 2q+1
  * passes and one m x (2q+2)l x n product form gA.
  *   gA : m x n, a_dtype, stride ldga (written)
- * Requires opts->prec == TSSVD_PREC_FP64 and working_precision <= 0.
+ * Requires opts->prec == TSSVD_PREC_FP64, working_precision <= 0 and no TSSVD_FLAG_GRAM
+ * (TSSVD_E_UNSUPPORTED otherwise).
  * ------------------------------------------------------------------------------------- */
 int lowrank_svd_backward_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t l,
                                          int64_t q, int32_t a_dtype, const tssvd_opts* opts,

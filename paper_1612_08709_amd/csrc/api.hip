@@ -693,6 +693,27 @@ int lowrank_check(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t 
   return TSSVD_OK;
 }
 
+// Discard rule of Algorithms 1-2 inside Algorithm 5 (wp > 0): the columns j of the
+// Householder Q whose |R_jj| < wp |R_11| (R the TSQR root, row-major l x l) are zeroed, so
+// the basis keeps only the numerically independent directions.  Gated (skipped when *gate
+// == 0); *kept (optional) receives the number of kept columns.
+__global__ void k_discard_cols(double* __restrict__ Y, int64_t rows, int l, int64_t ldy,
+                               const double* __restrict__ R, double wp,
+                               const int* __restrict__ gate, int* __restrict__ kept) {
+  if (gate && *gate == 0) return;
+  const double thr = wp * fabs(R[0]);
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx == 0 && kept) {
+    int r = 0;
+    for (int j = 0; j < l; ++j) r += !(fabs(R[j * l + j]) < thr);
+    *kept = r;
+  }
+  if (idx >= rows * l) return;
+  const int64_t i = idx / l;
+  const int j = (int)(idx - i * l);
+  if (fabs(R[j * l + j]) < thr) Y[i * ldy + j] = 0.0;
+}
+
 // Orthonormal basis of span(Y) by TSQR, written over Y (m x l).
 // Basis of an intermediate step (rows x l, row-major): R from the Cholesky factor of the
 // Gram Y^T Y (CholeskyQR), T = R^-1, Y kept.  The basis Y R^-1 loses orthogonality like
@@ -727,9 +748,12 @@ hipError_t gram_basis(const double* Y, int64_t rows, int l, double wp, int sweep
 constexpr double kKappaMax = 1e4;
 hipError_t basis_via_r(const TsqrPlan& p, double* Y, int64_t rows, int l, const double* I,
                        double* T, double* G, double* Rc, double* part, int* flags,
-                       hipStream_t s) {
+                       hipStream_t s, double wp = 0.0) {
   int* use_q = flags;
   int* chol_bad = flags + 1;
+  // wp > 0 (the paper's discard): every basis is the TSQR's Householder Q, with the
+  // discard applied on its R; kappa_max = 0 makes the device gate take that branch
+  const double kmax = (wp > 0.0) ? 0.0 : kKappaMax;
   hipError_t e = gemm_atq_f64(Y, TSSVD_F64, l, rows, l, Y, l, l, G, l, part, s);  // Y^T Y
   if (e != hipSuccess) return e;
   static bool attr_set = false;  // the attribute is per function; setting it twice is harmless
@@ -743,25 +767,29 @@ hipError_t basis_via_r(const TsqrPlan& p, double* Y, int64_t rows, int l, const 
     attr_set = true;
   }
   if (l <= 16) {
-    hipLaunchKernelGGL(k_chol_rinv_gate<16>, dim3(1), dim3(64), 0, s, G, l, kKappaMax, T, use_q,
+    hipLaunchKernelGGL(k_chol_rinv_gate<16>, dim3(1), dim3(64), 0, s, G, l, kmax, T, use_q,
                        chol_bad);
   } else if (l <= 32) {
-    hipLaunchKernelGGL(k_chol_rinv_gate<32>, dim3(1), dim3(64), 0, s, G, l, kKappaMax, T, use_q,
+    hipLaunchKernelGGL(k_chol_rinv_gate<32>, dim3(1), dim3(64), 0, s, G, l, kmax, T, use_q,
                        chol_bad);
   } else if (l <= 64) {
-    hipLaunchKernelGGL(k_chol_rinv_gate<64>, dim3(1), dim3(64), 0, s, G, l, kKappaMax, T, use_q,
+    hipLaunchKernelGGL(k_chol_rinv_gate<64>, dim3(1), dim3(64), 0, s, G, l, kmax, T, use_q,
                        chol_bad);
   } else {
     hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), (size_t)l * l * sizeof(double), s, G, l, Rc,
                        chol_bad);
     hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), (size_t)l * l * sizeof(double),
-                       s, Rc, l, kKappaMax, T, use_q, chol_bad);
+                       s, Rc, l, kmax, T, use_q, chol_bad);
   }
   TsqrPlan pq = p;
   pq.gate = use_q;
   e = tsqr_factor(pq, Y, TSSVD_F64, l, s);
   if (e != hipSuccess) return e;
-  return tsqr_apply(pq, I, l, Y, l, s);
+  e = tsqr_apply(pq, I, l, Y, l, s);
+  if (e != hipSuccess || !(wp > 0.0)) return e;
+  hipLaunchKernelGGL(k_discard_cols, dim3((unsigned)((rows * l + 255) / 256)), dim3(256), 0, s, Y,
+                     rows, l, (int64_t)l, tsqr_root(pq), wp, use_q, nullptr);
+  return hipGetLastError();
 }
 
 hipError_t orth_inplace(const TsqrPlan& p, double* Y, int l, const double* I, hipStream_t s) {
@@ -797,7 +825,7 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   const bool mixed = o.prec == TSSVD_PREC_MIXED;
   if (mixed && a_dtype != TSSVD_F32) return TSSVD_E_INVALID_ARG;
   const bool gram = (o.flags & TSSVD_FLAG_GRAM) != 0;
-  if (o.working_precision > 0.0 && !gram) return TSSVD_E_UNSUPPORTED;
+  const double wp = o.working_precision;  // > 0: the paper's discard rule (rank-deficient mode)
   const int ki = (int)k, li = (int)l;
   const bool acopy = mixed && q >= 1 && !(o.flags & TSSVD_FLAG_NO_A_COPY);
   LowrankWs w = lowrank_layout(m, n, ki, li, work, mixed, acopy);
@@ -854,7 +882,8 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   int* use_q = w.gate + 1;
   int* grank = w.gpos + li;
   auto basis = [&](const TsqrPlan& p, double* Yb, int64_t rows) -> hipError_t {
-    if (!gram) return basis_via_r(p, Yb, rows, li, w.I, w.Tq, w.G, w.Rc, w.part, use_q, s);
+    if (!gram)
+      return basis_via_r(p, Yb, rows, li, w.I, w.Tq, w.G, w.Rc, w.part, use_q, s, wp);
     return gram_basis(Yb, rows, li, o.working_precision, o.max_jacobi_sweeps, w.G, w.W, w.P,
                       w.sig, p.Vleaf, w.gsum, w.gnrm, w.gscale, w.gpos, grank, w.Tq, w.part,
                       info, s);
@@ -884,16 +913,24 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
     TRY(gemm_ax_f64(Y1, TSSVD_F64, l, m, l, w.Tq, li, li, w.Y, li, s));      // Q
   } else {
     TRY(orth_inplace(w.pY, w.Y, li, w.I, s));                                  // Q
+    if (wp > 0.0)
+      hipLaunchKernelGGL(k_discard_cols, dim3((unsigned)((m * l + 255) / 256)), dim3(256), 0, s,
+                         w.Y, m, li, l, tsqr_root(w.pY), wp, nullptr, grank);
   }
   if (!gram && o.ortho != TSSVD_ORTHO_ONCE) {
-    // last step orthonormalized twice (Algorithm 2 form), gated like tssvd
+    // last step orthonormalized twice (Algorithm 2 form), gated like tssvd; with the discard
+    // the second pass always runs (Algorithm 2) and applies the rule again
     TRY(gemm_atq_f64(w.Y, TSSVD_F64, l, m, l, w.Y, li, li, w.G, li, w.part, s));
-    hipLaunchKernelGGL(k_ortho_gate, dim3(1), dim3(256), 0, s, w.G, li, o.ortho, o.reorth_tol,
-                       w.ortho, w.gate, info);
+    hipLaunchKernelGGL(k_ortho_gate, dim3(1), dim3(256), 0, s, w.G, li,
+                       wp > 0.0 ? (int)TSSVD_ORTHO_TWICE : o.ortho, o.reorth_tol, w.ortho,
+                       w.gate, info);
     TsqrPlan p2 = w.pY;
     p2.gate = w.gate;
     TRY(tsqr_factor(p2, w.Y, TSSVD_F64, l, s));
     TRY(tsqr_apply(p2, w.I, li, w.Y, l, s));
+    if (wp > 0.0)
+      hipLaunchKernelGGL(k_discard_cols, dim3((unsigned)((m * l + 255) / 256)), dim3(256), 0, s,
+                         w.Y, m, li, l, tsqr_root(p2), wp, w.gate, grank);
   }
   // Algorithm 6: B = Q^* A via B^* = A^* Q = Q_B R_B;  R_B^T = P S W^T  =>
   //   B = P S (Q_B W)^T,  U = Q P_k,  V = Q_B W_k.
@@ -901,7 +938,7 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   TRY(tsqr_factor(w.pZ, w.Z, TSSVD_F64, l, s));
   TRY(jacobi_svd(tsqr_root(w.pZ), li, li, 1, 0.0, o.max_jacobi_sweeps, 0, w.P, w.sig, w.W,
                  info, s));
-  if (gram)  // directions dropped by the discard carry rounding-level singular values
+  if (gram || wp > 0.0)  // directions dropped by a discard carry rounding-level values
     hipLaunchKernelGGL(k_truncate_rank, dim3((li * li + 255) / 256), dim3(256), 0, s, grank,
                        w.sig, w.P, li, w.W, li, li, info);
   TRY(copy_matrix(w.W, l, ki, l, w.Wk, k, s));
@@ -1004,7 +1041,8 @@ int lowrank_svd_backward(const void* A, int32_t a_dtype, int64_t m, int64_t n, i
   if (!gA || ldga < n || ldu < k || ldv < k) return TSSVD_E_INVALID_ARG;
   const tssvd_opts o = resolve(opts);
   if (check_opts(o) != TSSVD_OK) return TSSVD_E_INVALID_ARG;
-  if (o.prec != TSSVD_PREC_FP64 || o.working_precision > 0.0) return TSSVD_E_UNSUPPORTED;
+  if (o.prec != TSSVD_PREC_FP64 || o.working_precision > 0.0 || (o.flags & TSSVD_FLAG_GRAM))
+    return TSSVD_E_UNSUPPORTED;
   (void)U; (void)S; (void)V;  // the forward is recomputed from (A, Omega); see the header
   const int ki = (int)k, li = (int)l, qi = (int)q;
   BackwardWs w = backward_layout(m, n, ki, li, qi, work);

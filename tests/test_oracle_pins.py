@@ -236,6 +236,25 @@ def test_alg8_reproduces_printed_error(l):
         assert checks.maxentry_ortho(V, r) < 10 * g["mv"]
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("l", [20, 10])
+def test_devils_staircase_lowrank_errors_at_rounding_level(l):
+    """Appendix B tables tab56*18new and partialSVDerr18new: on Devil's-staircase spectra
+    (repeated values, one zero, k = l) Algorithms 7 and 8 print errors of 2.2e-15 .. 8.7e-15
+    and orthonormality near eps.  Both oracle routes stay below 1e-14, keep exactly the
+    nonzero values, and recover them to rounding."""
+    sigma = sm.staircase(l)
+    A = sm.dct_planted(10_000, 2_000, sigma)
+    Om = sm.gaussian((2_000, l), 93, "omega", l)
+    for ref in (lowrank_ref, lowrank_gram_ref):
+        U, s, V = ref(A, Om, l, 2, wp=1e-11)
+        r = int(np.count_nonzero(s))
+        assert r == int(np.count_nonzero(sigma))
+        assert checks.spectral_residual(A, U, s, V, iters=20) < 1e-14
+        assert np.max(np.abs(s[:r] - sigma[:r])) < 1e-14
+        assert checks.maxentry_ortho(U, r) < 1e-14 and checks.maxentry_ortho(V, r) < 1e-14
+
+
 def test_alg8_exact_rank_reduces_to_textbook_svd():
     """rank(A) = l: the Gram route also returns the exact top-k SVD (numpy), q = 0 and 2."""
     m, n, l, k = 400, 120, 10, 6
