@@ -77,8 +77,13 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(
           p = t;
           q = np - 1;
         } else {
-          p = (t + grp) % (np - 1);
-          q = (t - grp + (np - 1)) % (np - 1);
+          // (t + grp) mod (np - 1) and (t - grp) mod (np - 1): both sums lie within one
+          // period of the range (0 <= t < np - 1, 0 < grp < np / 2), so a conditional
+          // subtraction or addition replaces the integer divisions
+          p = t + grp;
+          if (p >= np - 1) p -= np - 1;
+          q = t - grp;
+          if (q < 0) q += np - 1;
         }
         if (p > q) { const int tmp = p; p = q; q = tmp; }
         if (q < n) {
