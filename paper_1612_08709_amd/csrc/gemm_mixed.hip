@@ -484,7 +484,7 @@ constexpr int MX_COLS = 256;
 #define AX_RT 4
 #endif
 #ifndef AX_RT3
-#define AX_RT3 4
+#define AX_RT3 8  // rows per wave 128: halves the fragment bytes per byte of A (occupancy 1 either way)
 #endif
 
 __device__ __forceinline__ void mx_tile(int total, int ncol, int& chunk, int& ct, bool& ok) {
