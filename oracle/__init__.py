@@ -12,6 +12,7 @@ Modules
   tssvd_ref   Algorithms 1 and 2 (tall-skinny SVD, single / double orthonormalization)
   lowrank_ref Algorithms 5, 6 and 7 (randomized subspace iteration + direct SVD)
   gram_ref    Algorithms 3 and 4 (Gram-based tall-skinny SVD) and Algorithm 8
+  lu_ref      LU with partial pivoting as the tracking basis of Algorithm 5 (Section 3)
   grad_ref    vector-Jacobian product of the low-rank forward (torch float64 autograd)
   checks      orthonormality and spectral-norm error metrics (Table "heads")
   signs       the output sign convention
@@ -25,5 +26,6 @@ do not come from the function itself (printed table values, closed forms,
 from .checks import gram_pairwise, maxentry_ortho, ortho_spec, spectral_residual  # noqa: F401
 from .gram_ref import gram_svd_ref, lowrank_gram_ref  # noqa: F401
 from .lowrank_ref import lowrank_ref  # noqa: F401
+from .lu_ref import lu_basis, lu_factor_gepp  # noqa: F401
 from .signs import sign_reference, apply_sign_rule  # noqa: F401
 from .tssvd_ref import discard_rule, tssvd_ref, tsqr_ref  # noqa: F401

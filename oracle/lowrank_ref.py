@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from .lu_ref import lu_basis
 from .signs import apply_sign_rule
 from .tssvd_ref import tsqr_ref
 
@@ -48,9 +49,11 @@ def _at_times(A: np.ndarray, Q: np.ndarray) -> np.ndarray:
 
 
 def lowrank_ref(A: np.ndarray, Omega: np.ndarray, k: int, q: int, wp: float = 0.0,
-                mixes=None, return_basis: bool = False):
+                mixes=None, return_basis: bool = False, tracking: str = "qr"):
     """Rank-k approximation U diag(sigma) V^T of A via Algorithm 7.
 
+    tracking="lu" takes the intermediate bases of Algorithm 5 from an LU factorization
+    with partial pivoting (``oracle.lu_ref``) instead of QR; the last step is unchanged.
     Returns (U m x k, sigma k, V n x k[, Q]).  Columns past the numerical rank
     are zero with sigma = 0.
     """
@@ -59,15 +62,18 @@ def lowrank_ref(A: np.ndarray, Omega: np.ndarray, k: int, q: int, wp: float = 0.
     l = Omega.shape[1]
     if not (0 < k <= l < min(m, n)):
         raise ValueError("need 0 < k <= l < min(m, n)")
+    if tracking not in ("qr", "lu") or (tracking == "lu" and (wp > 0.0 or mixes is not None)):
+        raise ValueError("tracking is 'qr', or 'lu' without the discard rule")
 
     def orth(Y):
         mix = mixes(Y.shape[1]) if (mixes is not None and Y.shape[1] > 0) else None
         return tsqr_ref(Y, wp, mix)[0]
 
+    track = orth if tracking == "qr" else lu_basis
     Qt = Omega                                          # step 1
     for _ in range(q):                                  # steps 2-7
-        Qj = orth(_a_times(A, Qt))                      # Y_j = A Q~_{j-1};  Y_j = Q_j R_j
-        Qt = orth(_at_times(A, Qj))                     # Y~_j = A^* Q_j;  Y~_j = Q~_j R~_j
+        Qj = track(_a_times(A, Qt))                     # Y_j = A Q~_{j-1};  Y_j = Q_j R_j
+        Qt = track(_at_times(A, Qj))                    # Y~_j = A^* Q_j;  Y~_j = Q~_j R~_j
     Q = tsqr_ref(orth(_a_times(A, Qt)), wp)[0]          # last step, orthonormalized twice (Alg. 2)
     B = _at_times(A, Q).T                               # Alg. 6: B = Q^* A  (r x n)
     Ub, s, Vh = np.linalg.svd(B, full_matrices=False)   # B = U~ Sigma V^*

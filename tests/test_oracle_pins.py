@@ -14,6 +14,7 @@ import oracle
 from oracle import checks, grad_ref, philox
 from oracle.gram_ref import alg3, alg4, gram_svd_ref, lowrank_gram_ref
 from oracle.lowrank_ref import lowrank_ref
+from oracle.lu_ref import lu_basis, lu_factor_gepp
 from oracle.tssvd_ref import discard_rule, tssvd_ref, tsqr_ref
 from synth import matrices as sm
 
@@ -284,6 +285,77 @@ def test_lowrank_exact_rank_reduces_to_textbook_svd():
         for j in range(k):
             assert _subspace_cos(U[:, j], Ue[:, j]) > 1 - 1e-12
             assert _subspace_cos(V[:, j], Vhe[j]) > 1 - 1e-12
+
+
+# ---------------------------------------------------------------- LU tracking (Section 3)
+def test_gepp_hand_worked_example():
+    """3 x 2 elimination by hand: column 0 pivots on row 2 (|5|), multipliers 1/5 and 3/5
+    leave 2 - 6/5 = 0.8 and 4 - 18/5 = 0.4; column 1 pivots on row 0 (0.8), multiplier 0.5.
+    U = [[5, 6], [0, 0.8]]; the basis Y U^-1 in Y's row order is [0.2, 1], [0.6, 0.5], [1, 0]."""
+    Y = np.array([[1.0, 2.0], [3.0, 4.0], [5.0, 6.0]])
+    rows, L, U = lu_factor_gepp(Y)
+    assert list(rows) == [2, 0, 1]
+    np.testing.assert_allclose(U, [[5.0, 6.0], [0.0, 0.8]], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(L, [[1.0, 0.0], [0.2, 1.0], [0.6, 0.5]], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(lu_basis(Y), [[0.2, 1.0], [0.6, 0.5], [1.0, 0.0]], rtol=0,
+                               atol=1e-15)
+
+
+@pytest.mark.parametrize("m,l,sub", [(50, 7, 1), (300, 24, 2), (64, 64, 3)])
+def test_gepp_matches_lapack_partial_pivoting(m, l, sub):
+    """Gaussian inputs (no ties): the row order, L and U of LAPACK's getrf (scipy.linalg.lu)."""
+    import scipy.linalg
+    Y = sm.gaussian((m, l), workload=96, stream="A", sub=sub)
+    rows, L, U = lu_factor_gepp(Y)
+    P, Ls, Us = scipy.linalg.lu(Y)                     # Y = P Ls Us
+    np.testing.assert_array_equal(np.argmax(P, axis=0), rows)
+    np.testing.assert_allclose(L, Ls, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(U, Us, rtol=0, atol=1e-12 * np.abs(Us).max())
+    assert np.abs(L).max() <= 1.0
+
+
+def test_lu_basis_spans_the_columns_of_y():
+    """P^T L = Y U^-1 lies in range(Y) (projector from numpy's QR) and reproduces Y."""
+    Y = sm.gaussian((500, 12), workload=96, stream="A", sub=4) @ np.diag(np.logspace(0, -6, 12))
+    B = lu_basis(Y)
+    Q = np.linalg.qr(Y)[0]
+    assert np.linalg.norm(B - Q @ (Q.T @ B)) < 1e-13 * np.linalg.norm(B)
+    _, _, U = lu_factor_gepp(Y)
+    np.testing.assert_allclose(B @ U, Y, rtol=0, atol=1e-15 * np.abs(Y).max())
+
+
+def test_lowrank_lu_tracking_matches_qr_tracking():
+    """Both trackings carry the same column space, so Algorithm 7 gives the same result
+    (to rounding) with either; at q = 0 there is no intermediate basis and the two agree
+    exactly."""
+    m, n, l, k = 2000, 300, 20, 10
+    sigma = np.exp(-np.arange(n) / 8.0)
+    A = sm.planted(m, n, sigma, workload=97)
+    Om = sm.sketch(n, l, 97)
+    for q in (0, 1, 3):
+        Uq, sq, Vq = lowrank_ref(A, Om, k, q)
+        Ul, sl, Vl = lowrank_ref(A, Om, k, q, tracking="lu")
+        if q == 0:
+            np.testing.assert_array_equal(sl, sq)
+            np.testing.assert_array_equal(Ul, Uq)
+            continue
+        np.testing.assert_allclose(sl, sq, rtol=1e-12)
+        for j in range(k):
+            assert _subspace_cos(Ul[:, j], Uq[:, j]) > 1 - 1e-12
+            assert _subspace_cos(Vl[:, j], Vq[:, j]) > 1 - 1e-12
+
+
+def test_lowrank_lu_tracking_exact_rank_reduces_to_textbook_svd():
+    """rank(A) = l: the LU bases span range(A) too, so the exact top-k SVD (numpy) comes back."""
+    m, n, l, k = 400, 120, 10, 6
+    sigma = 1.0 / np.arange(1, l + 1)
+    A = sm.planted(m, n, sigma, workload=93)
+    U, s, V = lowrank_ref(A, sm.sketch(n, l, 93), k, 2, tracking="lu")
+    Ue, se, Vhe = np.linalg.svd(A, full_matrices=False)
+    np.testing.assert_allclose(s, se[:k], rtol=1e-12)
+    for j in range(k):
+        assert _subspace_cos(U[:, j], Ue[:, j]) > 1 - 1e-12
+        assert _subspace_cos(V[:, j], Vhe[j]) > 1 - 1e-12
 
 
 def test_lowrank_residual_near_optimal():
