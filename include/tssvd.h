@@ -107,6 +107,16 @@ typedef struct {
  * matrix squares the condition number: singular values below ~sqrt(eps) sigma_1 are not
  * resolved (the paper's trade of accuracy for one pass). */
 #define TSSVD_FLAG_GRAM 4
+/* lowrank_svd: LU-based subspace tracking (Section 3's remark on the power iterations).
+ * The intermediate bases of Algorithm 5 are L = Y U^-1 from an LU factorization of Y with
+ * tournament pivoting (Gaussian elimination with partial pivoting on groups of rows, the
+ * picked rows competing again up a tree) instead of an orthonormal Q; they span the same
+ * columns.  The last step keeps Algorithm 2's double orthonormalization, so the result is
+ * that of Algorithm 7 up to rounding.  A singular pivot block falls back to the Householder
+ * Q for that step.  Requires l <= 64 and working_precision <= 0 (TSSVD_E_UNSUPPORTED
+ * otherwise); TSSVD_FLAG_GRAM with it is TSSVD_E_INVALID_ARG.  Other entry points ignore
+ * the flag, except lowrank_svd_backward, which rejects it. */
+#define TSSVD_FLAG_LU 8
 
 /* Device-side record written (when non-NULL) at the end of every call. */
 typedef struct {
@@ -190,8 +200,8 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
  * l, q and options; they are not read.  2q+2 passes over A recompute the forward, 2q+1
  * passes and one m x (2q+2)l x n product form gA.
  *   gA : m x n, a_dtype, stride ldga (written)
- * Requires opts->prec == TSSVD_PREC_FP64, working_precision <= 0 and no TSSVD_FLAG_GRAM
- * (TSSVD_E_UNSUPPORTED otherwise).
+ * Requires opts->prec == TSSVD_PREC_FP64, working_precision <= 0 and neither
+ * TSSVD_FLAG_GRAM nor TSSVD_FLAG_LU (TSSVD_E_UNSUPPORTED otherwise).
  * ------------------------------------------------------------------------------------- */
 int lowrank_svd_backward_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t l,
                                          int64_t q, int32_t a_dtype, const tssvd_opts* opts,

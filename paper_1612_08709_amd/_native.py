@@ -22,6 +22,7 @@ NUM_NONFINITE, NUM_NO_CONVERGENCE = 1, 2
 FLAG_F32_MFMA_FINAL = 1
 FLAG_NO_A_COPY = 2
 FLAG_GRAM = 4
+FLAG_LU = 8
 
 # every exported symbol declared in include/tssvd.h
 EXPORTS = (

@@ -634,6 +634,7 @@ struct LowrankWs {
   double *X, *Y, *Z, *Zraw, *part, *I, *P, *sig, *W, *Wk, *G, *ortho, *Tq, *Rc;
   double *gsum, *gnrm, *gscale;  // Gram route (Algorithm 8): norms and column scales
   int* gpos;                     // Gram route: column places (l) and the kept rank
+  int* luidx;                    // LU tracking: tournament candidates
   void* pack;
   void* Acopy;  // bfloat16 copy of A for the mixed power steps (or null)
   int* gate;
@@ -680,6 +681,7 @@ LowrankWs lowrank_layout(int64_t m, int64_t n, int k, int l, void* work, bool mi
   w.gnrm = c.take<double>(l);
   w.gscale = c.take<double>(l);
   w.gpos = c.take<int>((size_t)l + 1);
+  w.luidx = c.take<int>(l <= LU_L_MAX ? lu_index_ints(m > n ? m : n, l) : 1);
   w.gate = c.take<int>(4);
   w.bytes = c.off + 256;
   return w;
@@ -792,6 +794,21 @@ hipError_t basis_via_r(const TsqrPlan& p, double* Y, int64_t rows, int l, const 
   return hipGetLastError();
 }
 
+// Basis of an intermediate step from an LU factorization (Section 3's remark on tracking):
+// T = U^-1 with U from the tournament-pivoted LU of Y, so that Y T = L (rows in Y's order).
+// A singular or non-finite U sets *use_q and falls back to the TSQR's Householder Q, as
+// for a rejected Cholesky basis.
+hipError_t basis_via_lu(const TsqrPlan& p, double* Y, int64_t rows, int l, const double* I,
+                        double* T, int* idx, int* use_q, hipStream_t s) {
+  hipError_t e = lu_tracking_T(Y, rows, l, l, idx, T, use_q, s);
+  if (e != hipSuccess) return e;
+  TsqrPlan pq = p;
+  pq.gate = use_q;
+  e = tsqr_factor(pq, Y, TSSVD_F64, l, s);
+  if (e != hipSuccess) return e;
+  return tsqr_apply(pq, I, l, Y, l, s);
+}
+
 hipError_t orth_inplace(const TsqrPlan& p, double* Y, int l, const double* I, hipStream_t s) {
   hipError_t e = tsqr_factor(p, Y, TSSVD_F64, l, s);
   if (e != hipSuccess) return e;
@@ -825,7 +842,10 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   const bool mixed = o.prec == TSSVD_PREC_MIXED;
   if (mixed && a_dtype != TSSVD_F32) return TSSVD_E_INVALID_ARG;
   const bool gram = (o.flags & TSSVD_FLAG_GRAM) != 0;
+  const bool lu = (o.flags & TSSVD_FLAG_LU) != 0;
   const double wp = o.working_precision;  // > 0: the paper's discard rule (rank-deficient mode)
+  if (lu && gram) return TSSVD_E_INVALID_ARG;
+  if (lu && (wp > 0.0 || l > LU_L_MAX)) return TSSVD_E_UNSUPPORTED;
   const int ki = (int)k, li = (int)l;
   const bool acopy = mixed && q >= 1 && !(o.flags & TSSVD_FLAG_NO_A_COPY);
   LowrankWs w = lowrank_layout(m, n, ki, li, work, mixed, acopy);
@@ -882,6 +902,7 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   int* use_q = w.gate + 1;
   int* grank = w.gpos + li;
   auto basis = [&](const TsqrPlan& p, double* Yb, int64_t rows) -> hipError_t {
+    if (lu) return basis_via_lu(p, Yb, rows, li, w.I, w.Tq, w.luidx, use_q, s);
     if (!gram)
       return basis_via_r(p, Yb, rows, li, w.I, w.Tq, w.G, w.Rc, w.part, use_q, s, wp);
     return gram_basis(Yb, rows, li, o.working_precision, o.max_jacobi_sweeps, w.G, w.W, w.P,
@@ -1041,7 +1062,8 @@ int lowrank_svd_backward(const void* A, int32_t a_dtype, int64_t m, int64_t n, i
   if (!gA || ldga < n || ldu < k || ldv < k) return TSSVD_E_INVALID_ARG;
   const tssvd_opts o = resolve(opts);
   if (check_opts(o) != TSSVD_OK) return TSSVD_E_INVALID_ARG;
-  if (o.prec != TSSVD_PREC_FP64 || o.working_precision > 0.0 || (o.flags & TSSVD_FLAG_GRAM))
+  if (o.prec != TSSVD_PREC_FP64 || o.working_precision > 0.0 ||
+      (o.flags & (TSSVD_FLAG_GRAM | TSSVD_FLAG_LU)))
     return TSSVD_E_UNSUPPORTED;
   (void)U; (void)S; (void)V;  // the forward is recomputed from (A, Omega); see the header
   const int ki = (int)k, li = (int)l, qi = (int)q;

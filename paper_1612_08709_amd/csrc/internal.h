@@ -94,6 +94,15 @@ hipError_t gram_any(const void* Y, int y_dtype, int64_t ldy, int64_t rows, int l
 hipError_t column_sumsq(const void* Y, int y_dtype, int64_t rows, int l, int64_t ldy, double* out,
                         double* part, hipStream_t s);
 size_t column_sumsq_partials(int64_t rows, int l);
+
+// ------------------------------------------------------------------ LU tracking bases
+// T = U^-1 for the tournament-pivoted LU factor U of Y (rows x l, float64, row-major,
+// stride ldy, rows >= l, l <= LU_L_MAX), so that Y T spans range(Y); *use_q (device) = 1
+// and T = I when U is singular or not finite.  idx: lu_index_ints(rows, l) ints.
+constexpr int LU_L_MAX = 64;
+size_t lu_index_ints(int64_t rows, int l);
+hipError_t lu_tracking_T(const double* Y, int64_t rows, int l, int64_t ldy, int* idx, double* T,
+                         int* use_q, hipStream_t s);
 hipError_t reduce_chunks(const double* part, int nchunk, int64_t n, int l, double* Z, int ldz,
                          hipStream_t s);
 
