@@ -441,6 +441,9 @@ def main():
     # the paper's other method on the same bytes: Algorithm 8 (Gram-based bases), mixed
     gram = run_lowrank(A, spec, T.PREC_MIXED, max(2, args.steps // 2), 1, 4, flags=T.FLAG_GRAM)
     gram_sig_diff = float(np.max(np.abs(gram["S"] - fp64["S"]) / fp64["S"]))
+    # Section 3's cheaper tracking: LU bases in the power steps, mixed
+    lu = run_lowrank(A, spec, T.PREC_MIXED, max(2, args.steps // 2), 1, 4, flags=T.FLAG_LU)
+    lu_sig_diff = float(np.max(np.abs(lu["S"] - fp64["S"]) / fp64["S"]))
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline_lowrank(A, mixed["Om"], spec, min(args.cpu_rows, spec["m"]))
@@ -498,6 +501,11 @@ def main():
                                     "prec": "mixed", "ortho_U": gram["ortho_u"],
                                     "ortho_V": gram["ortho_v"],
                                     "sigma_max_rel_diff_vs_fp64_alg7": gram_sig_diff},
+        "lu_tracking_same_workload": {"value": round(lu["value"], 2), "unit": "GB/s",
+                                      "ms_per_call": round(lu["sec"] * 1e3, 4),
+                                      "prec": "mixed", "ortho_U": lu["ortho_u"],
+                                      "ortho_V": lu["ortho_v"],
+                                      "sigma_max_rel_diff_vs_fp64_alg7": lu_sig_diff},
         "accuracy": {"ortho_U_2norm": mixed["ortho_u"], "ortho_V_2norm": mixed["ortho_v"],
                      "sigma_max_rel_diff_mixed_vs_fp64": sig_diff,
                      "gate_ortho_le_1e-12": bool(max(mixed["ortho_u"], mixed["ortho_v"]) <= 1e-12

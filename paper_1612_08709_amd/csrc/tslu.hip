@@ -12,51 +12,75 @@
 // pivoting keeps |L| moderate.
 #include "internal.h"
 
-#include <climits>
-
 namespace tsv {
 namespace {
 
 constexpr int LU_THREADS = 256;
+// Columns are handled in chunks of 8: a chunk past the meaningful columns is skipped, and
+// a chunk's 8 pivot-row values are loaded from LDS together before its 8 updates.
+constexpr int LU_CHUNK = 8;
 
-// Candidate order for the pivot search: a larger |value| wins, then a smaller row index.
-// key = (bit pattern of |v|) + 1 is monotone in |v| for |v| >= 0 (NaN sorts above +inf);
-// key 0 marks a lane with no candidate.
-__device__ __forceinline__ bool lu_better(unsigned long long ka, int ra, unsigned long long kb,
-                                          int rb) {
-  return ka > kb || (ka == kb && ra < rb);
+// Pivot search key of a candidate: the bit pattern of |v| (monotone in |v|; NaN sorts above
+// +inf) with its low 9 bits replaced by an "active" bit and 255 - t, so that a larger |v|
+// wins, then a smaller thread index, and every key in the workgroup is distinct.  Dropping
+// 9 of the 52 mantissa bits lets a value within a relative 2^-43 of the largest win, which
+// leaves partial pivoting's bound |multiplier| <= 1 + 2^-43.  Key 0: no candidate.
+__device__ __forceinline__ unsigned long long lu_key(double v, int t) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(v));
+  return (bits & ~0x1FFull) | 0x100ull | (unsigned long long)(255 - t);
 }
 
-__device__ __forceinline__ void wave_argmax(unsigned long long& key, int& row) {
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_max(unsigned long long key) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)key, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(key >> 32), CTRL, 0xF, 0xF, false);
+  const unsigned long long k2 = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+  return k2 > key ? k2 : key;
+}
+
+__device__ __forceinline__ unsigned long long lane_key(unsigned long long key, int lane) {
+  return ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(key >> 32), lane) << 32) |
+         (unsigned)__builtin_amdgcn_readlane((int)(unsigned)key, lane);
+}
+
+// Wave maximum of the keys, returned uniform: DPP exchanges within each row of 16 lanes
+// (quad swaps, half-row mirror, row mirror), then the four row maxima by readlane.
+__device__ __forceinline__ unsigned long long wave_max_key(unsigned long long key) {
+  key = dpp_max<0xB1>(key);
+  key = dpp_max<0x4E>(key);
+  key = dpp_max<0x141>(key);
+  key = dpp_max<0x140>(key);
+  unsigned long long best = lane_key(key, 0);
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const unsigned long long k2 = __shfl_xor(key, off);
-    const int r2 = __shfl_xor(row, off);
-    if (lu_better(k2, r2, key, row)) {
-      key = k2;
-      row = r2;
-    }
+  for (int q = 1; q < 4; ++q) {
+    const unsigned long long k2 = lane_key(key, 16 * q);
+    best = k2 > best ? k2 : best;
   }
+  return best;
 }
 
 // One level of the tournament.  Workgroup b's candidates: rows b*256 + t of Y at the leaf
 // level (cand == nullptr), else cand[b*per + t] for t < per (-1: none).  Thread t keeps its
-// candidate row (l <= LM entries) in registers.  Step j: the wave argmax of |r_j|, one
-// barrier, the winner of the four waves is the pivot row p; every remaining candidate
-// takes f = r_j / p_j and r_c -= f p_c for c > j.  The picked rows go to out[b*l + j] in
-// pivot order (-1 once the workgroup has no candidate left).
-// With one workgroup (the last level) the kernel also writes T = U^-1 (l x l, row-major)
-// by back substitution, thread j solving U t = e_j, and *use_q = 1 with T = I when a pivot
-// is zero or T is not finite.
+// candidate row in registers, shifted so that r[0] is always the column of the current
+// step: at step j, r[c] holds column j + c.  Step j: the wave maximum of the keys of
+// |r[0]|, one barrier, the best of the four waves' candidates is the pivot row p; every
+// remaining candidate takes f = r[0] / p[0] and r[c] = r[c+1] - f p[c+1] (update and shift
+// in one fused multiply-add).  The pivot row leaves the candidates with its registers
+// holding row j of U (shifted); after the last step each pivot thread writes its row index
+// to out[b*l + j] (pivot order; -1 where the workgroup ran out of candidates).
+// With one workgroup (the last level) the pivot threads also write U to LDS, and the
+// kernel writes T = U^-1 (l x l, row-major), thread t solving U x = e_t by the column sweep
+// from the bottom: with d[c] = b_{p-c}, x_p = d[0] / U_pp and d[c] = d[c+1] - U_{p-1-c,p} x_p.
+// *use_q = 1 and T = I when a pivot is zero or x is not finite.
 template <int LM>
 __global__ __launch_bounds__(LU_THREADS) void k_tslu_level(
     const double* __restrict__ Y, int64_t rows, int l, int64_t ldy, const int* __restrict__ cand,
     int64_t ncand, int per, int* __restrict__ out, double* __restrict__ T,
     int* __restrict__ use_q) {
   __shared__ unsigned long long skey[2][LU_THREADS / 64];
-  __shared__ int srow[2][LU_THREADS / 64];
-  __shared__ double prow[2][LU_THREADS / 64][LM];
-  __shared__ double Ut[LM][LM];  // last level: Ut[c][j] = U_jc
+  __shared__ double prow[2][LU_THREADS / 64][LM + 1];
+  __shared__ double Ur[LM][LM];  // last level: Ur[p][c] = U_{p-1-c, p} (column p upward)
+  __shared__ double Ud[LM];      // last level: U_pp
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t b = blockIdx.x;
   const bool last = gridDim.x == 1;
@@ -76,92 +100,102 @@ __global__ __launch_bounds__(LU_THREADS) void k_tslu_level(
 #pragma unroll
     for (int c = 0; c < LM; ++c) r[c] = 0.0;
   }
-  if (last)
-    for (int i = t; i < LM * LM; i += LU_THREADS) (&Ut[0][0])[i] = 0.0;
+  if (last) {
+    for (int i = t; i < LM * LM; i += LU_THREADS) (&Ur[0][0])[i] = 0.0;
+    if (t < LM) Ud[t] = 0.0;
+  }
   bool active = row >= 0;
-  bool more = true;  // uniform: some candidate is left
-  // runtime loop over the steps; the register arrays are indexed only by unrolled constants
+  int mystep = -1;  // the step at which this thread's row became the pivot
   int j = 0;
 #pragma unroll 1
-  for (; j < l && more; ++j) {
+  for (; j < l; ++j) {
     const int buf = j & 1;
-    double rj = 0.0;
+    const unsigned long long key = active ? lu_key(r[0], t) : 0ull;
+    const unsigned long long wk = wave_max_key(key);
+    if (wk != 0ull && key == wk) {  // this wave's candidate (keys are distinct)
+      skey[buf][wave] = wk;
+      // positions 0 .. l-1-j hold columns j .. l-1; the rest is never read
 #pragma unroll
-    for (int c = 0; c < LM; ++c)
-      if (c == j) rj = r[c];
-    unsigned long long key =
-        active ? (unsigned long long)__double_as_longlong(fabs(rj)) + 1ull : 0ull;
-    int who = active ? row : INT_MAX;
-    wave_argmax(key, who);
-    if (active && row == who) {  // the wave's pivot candidate (rows are distinct)
-      skey[buf][wave] = key;
-      srow[buf][wave] = who;
+      for (int cc = 0; cc < LM; cc += LU_CHUNK)
+        if (cc < l - j) {
 #pragma unroll
-      for (int c = 0; c < LM; ++c) prow[buf][wave][c] = r[c];
-    } else if (lane == 0 && key == 0ull) {
+          for (int u = 0; u < LU_CHUNK; ++u) prow[buf][wave][cc + u] = r[cc + u];
+        }
+    } else if (lane == 0 && wk == 0ull) {
       skey[buf][wave] = 0ull;
-      srow[buf][wave] = INT_MAX;
     }
     __syncthreads();
     unsigned long long bk = skey[buf][0];
-    int br = srow[buf][0], bw = 0;
+    int bw = 0;
 #pragma unroll
     for (int w = 1; w < LU_THREADS / 64; ++w) {
-      if (lu_better(skey[buf][w], srow[buf][w], bk, br)) {
-        bk = skey[buf][w];
-        br = srow[buf][w];
+      const unsigned long long k2 = skey[buf][w];
+      if (k2 > bk) {
+        bk = k2;
         bw = w;
       }
     }
-    if (bk == 0ull) {
-      more = false;
-    } else {
+    if (bk == 0ull) break;  // uniform: no candidate left
+    if (key == bk) {        // the pivot row: it keeps r (= row j of U, shifted) from here on
+      active = false;
+      mystep = j;
+    }
+    if (active) {
       const double* pr = prow[buf][bw];
-      if (last && t >= j && t < l) Ut[t][j] = pr[t];
-      if (active && row == br) active = false;
-      if (active) {
-        const double pj = pr[j];
-        const double f = (pj != 0.0) ? rj / pj : 0.0;
+      const double p0 = pr[0];
+      const double f = (p0 != 0.0) ? r[0] / p0 : 0.0;
+      // new positions 0 .. l-2-j are meaningful; a chunk past them is skipped (its
+      // registers keep stale values, which no meaningful position ever reads)
 #pragma unroll
-        for (int c = 0; c < LM; ++c) {
-          const double upd = fma(-f, pr[c], r[c]);
-          r[c] = (c > j) ? upd : r[c];
+      for (int cc = 0; cc < LM; cc += LU_CHUNK) {
+        if (cc < l - 1 - j) {
+          double q[LU_CHUNK];
+#pragma unroll
+          for (int u = 0; u < LU_CHUNK; ++u) q[u] = pr[cc + u + 1];
+#pragma unroll
+          for (int u = 0; u < LU_CHUNK; ++u)
+            r[cc + u] = fma(-f, q[u], (cc + u + 1 < LM) ? r[cc + u + 1] : 0.0);
         }
       }
     }
-    if (t == 0) out[b * l + j] = more ? br : -1;
   }
+  if (mystep >= 0) out[b * l + mystep] = row;
   if (t == 0)
-    for (; j < l; ++j) out[b * l + j] = -1;  // fewer than l candidates in this workgroup
-  if (!last) return;
-  __syncthreads();  // Ut complete
-  double x[LM];
+    for (int jj = j; jj < l; ++jj) out[b * l + jj] = -1;  // fewer than l candidates here
+  if (last && mystep >= 0) {
+    // U_{s, s+k} = r[k] for the pivot row of step s
+    Ud[mystep] = r[0];
 #pragma unroll
-  for (int i = 0; i < LM; ++i) x[i] = (i == t) ? 1.0 : 0.0;
-  // column sweep: x_p = x_p / U_pp, then x_i -= U_ip x_p for i < p
+    for (int k = 1; k < LM; ++k)
+      if (mystep + k < l) Ur[mystep + k][k - 1] = r[k];
+  }
+  if (!last) return;
+  __syncthreads();  // Ur, Ud complete
+  double d[LM];
+#pragma unroll
+  for (int c = 0; c < LM; ++c) d[c] = (l - 1 - c == t) ? 1.0 : 0.0;
+  int ok = 1;
 #pragma unroll 1
   for (int p = l - 1; p >= 0; --p) {
-    double xp = 0.0;
+    const double xp = d[0] / Ud[p];
+    ok &= isfinite(xp) ? 1 : 0;
+    if (t < l) T[(int64_t)p * l + t] = xp;
+    const double* up = Ur[p];
 #pragma unroll
-    for (int i = 0; i < LM; ++i)
-      if (i == p) xp = x[i];
-    xp = xp / Ut[p][p];
+    for (int cc = 0; cc < LM; cc += LU_CHUNK) {
+      if (cc < p) {
+        double q[LU_CHUNK];
 #pragma unroll
-    for (int i = 0; i < LM; ++i) {
-      const double upd = fma(-Ut[p][i], xp, x[i]);
-      x[i] = (i < p) ? upd : ((i == p) ? xp : x[i]);
+        for (int u = 0; u < LU_CHUNK; ++u) q[u] = up[cc + u];
+#pragma unroll
+        for (int u = 0; u < LU_CHUNK; ++u)
+          d[cc + u] = fma(-q[u], xp, (cc + u + 1 < LM) ? d[cc + u + 1] : 0.0);
+      }
     }
   }
-  double ss = 0.0;
-#pragma unroll
-  for (int i = 0; i < LM; ++i) ss = fma(x[i], x[i], ss);
-  const int ok = (t >= l) || isfinite(ss);
-  const int bad = __syncthreads_or(!ok);
-  if (t < l) {
-#pragma unroll
-    for (int i = 0; i < LM; ++i)
-      if (i < l) T[(int64_t)i * l + t] = bad ? (i == t ? 1.0 : 0.0) : x[i];
-  }
+  const int bad = __syncthreads_or((t < l) && !ok);
+  if (bad && t < l)
+    for (int i = 0; i < l; ++i) T[(int64_t)i * l + t] = (i == t) ? 1.0 : 0.0;
   if (t == 0) *use_q = bad;
 }
 
