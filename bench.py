@@ -235,7 +235,7 @@ def traffic_of(name):
     return rec
 
 
-def summarize_trace(d, command):
+def summarize_trace(d, command, by_grid=None):
     """Markdown summary of a rocprofv3 --kernel-trace --stats run (per-kernel statistics)."""
     import csv
     import glob
@@ -269,7 +269,35 @@ def summarize_trace(d, command):
     lines += ["", f"Other kernels (torch and ROCm libraries: generating the synthetic matrices "
                   f"and the accuracy checks, outside the timed region): {other_calls} calls, "
                   f"{other_ms:.1f} ms."]
+    if by_grid:
+        lines += by_grid_table(d, by_grid)
     return "\n".join(lines)
+
+
+def by_grid_table(d, pattern):
+    """Launches of the kernels matching `pattern`, grouped by grid size (workgroups)."""
+    import csv
+    import glob
+    import re
+    path = os.path.join(d, "run_kernel_trace.csv")
+    if not os.path.exists(path):
+        path = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)[0]
+    groups = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if not re.search(pattern, r["Kernel_Name"]):
+                continue
+            grid = int(r.get("Grid_Size_X") or r.get("Grid_Size"))
+            wg = int(r.get("Workgroup_Size_X") or r.get("Workgroup_Size"))
+            dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            groups.setdefault(grid // wg, []).append(dur)
+    lines = ["", f"Launches of kernels matching `{pattern}` by grid size:", "",
+             "| workgroups | launches | average us | min us | max us |", "|---|---|---|---|---|"]
+    for g in sorted(groups):
+        v = groups[g]
+        lines.append(f"| {g} | {len(v)} | {sum(v) / len(v) / 1e3:.1f} | {min(v) / 1e3:.1f} | "
+                     f"{max(v) / 1e3:.1f} |")
+    return lines
 
 
 def roofline_of(kernels):
@@ -407,6 +435,9 @@ def main():
                          "(FETCH_SIZE, WRITE_SIZE) and exit")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="print a summary of a rocprofv3 --kernel-trace --stats folder and exit")
+    ap.add_argument("--by-grid", metavar="REGEX",
+                    help="with --summarize-trace: also list the launches of the matching "
+                         "kernels by grid size")
     ap.add_argument("--command", default="",
                     help="the profiling command, recorded in a summary")
     args = ap.parse_args()
@@ -414,7 +445,7 @@ def main():
         print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.command))
         return
     if args.summarize_trace:
-        print(summarize_trace(args.summarize_trace, args.command))
+        print(summarize_trace(args.summarize_trace, args.command, args.by_grid))
         return
     global SIMPLE_DATA
     SIMPLE_DATA = args.simple_data

@@ -15,7 +15,8 @@
 namespace tsv {
 namespace {
 
-constexpr int LU_THREADS = 256;
+constexpr int LU_THREADS = 256;  // 512 (fan-in 8) measured slower: more waves per barrier
+constexpr int LU_TBITS = 8;       // bits of a thread index
 // Columns are handled in chunks of 8: a chunk past the meaningful columns is skipped, and
 // a chunk's 8 pivot-row values are loaded from LDS together before its 8 updates.
 constexpr int LU_CHUNK = 8;
@@ -27,7 +28,8 @@ constexpr int LU_CHUNK = 8;
 // leaves partial pivoting's bound |multiplier| <= 1 + 2^-43.  Key 0: no candidate.
 __device__ __forceinline__ unsigned long long lu_key(double v, int t) {
   const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(v));
-  return (bits & ~0x1FFull) | 0x100ull | (unsigned long long)(255 - t);
+  constexpr unsigned long long low = (1ull << (LU_TBITS + 1)) - 1;
+  return (bits & ~low) | (1ull << LU_TBITS) | (unsigned long long)(LU_THREADS - 1 - t);
 }
 
 template <int CTRL>
