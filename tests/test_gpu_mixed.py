@@ -136,3 +136,13 @@ def test_workload4_full_size():
     ef = residual_gpu(A, Uf, Sf, Vf)
     flush_print(f"  residual mixed {em:.9e} fp64 {ef:.9e} diff {abs(em - ef):.2e}")
     assert abs(em - ef) <= 1e-6 * sf_[0]
+    # Algorithm 6 gives V diag(S) = A^T U exactly (A^T Q P_k = Q_B R_B P_k = Q_B W_k S_k);
+    # sampled rows j of V S against FP64 dot products of column j of A with U on the host
+    cols = np.sort(np.random.default_rng(4).choice(n, 12, replace=False))
+    Acols = host(A[:, torch.from_numpy(cols).to(A.device)]).astype(np.float64)   # m x 12
+    for name, U_, S_, V_, tol in (("mixed", Um, sm_, Vm, 1e-6), ("fp64", Uf, sf_, Vf, 1e-12)):
+        ref = Acols.T @ host(U_)                                                   # 12 x k
+        got = host(V_)[cols] * S_
+        err = float(np.max(np.abs(got - ref))) / sf_[0]
+        flush_print(f"  sampled V S vs A^T U ({name}): {err:.2e} of sigma_1")
+        assert err <= tol

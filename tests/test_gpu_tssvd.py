@@ -134,3 +134,35 @@ def test_tsqr_float32_input():
     torch.cuda.synchronize()
     Q, R = host(Q), host(R)
     np.testing.assert_allclose(Q @ R, A32.astype(np.float64), atol=1e-12)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_workload3_full_size(dtype):
+    """4,000,000 x 100 (sigma log-spaced 1 .. 1e-6), stored float64 or float32, Algorithm 1
+    as the benchmark times it.  Properties at full size: orthonormality of U and V, sigma
+    against the planted values (float64 storage; float32 rounding moves the small ones),
+    and, for sampled rows i, U[i, :] diag(S) = A[i, :] V (A = U S V^T) against FP64 dot
+    products on the host."""
+    from synth import torch_gen
+    spec = sm.workload_spec(3)
+    m, n = spec["m"], spec["n"]
+    flush_print("case workload3 generate", dtype)
+    A = torch_gen.planted(m, n, spec["sigma"], 3, "cuda:0", dtype=dtype)
+    U, S, V, info = T.tssvd(A, ortho=T.ORTHO_ONCE)
+    torch.cuda.synchronize()
+    from gpu_util import ortho_gpu
+    ou, ov = ortho_gpu(U), ortho_gpu(V)
+    s_, v_ = host(S), host(V)
+    flush_print(f"  ortho U {ou:.2e} V {ov:.2e}; sigma rel vs planted "
+                f"{sigma_rel(s_, spec['sigma']):.2e}")
+    assert ou <= 5e-13 and ov <= 1e-13
+    assert np.all(np.diff(s_) <= 0)
+    if dtype == torch.float64:
+        assert sigma_rel(s_, spec["sigma"]) <= 1e-12
+    rows = np.sort(np.random.default_rng(3).choice(m, 64, replace=False))
+    idx = torch.from_numpy(rows).to(A.device)
+    Arows = host(A[idx]).astype(np.float64)                                   # 64 x n
+    err = float(np.max(np.abs(host(U[idx]) * s_ - Arows @ v_))) / s_[0]
+    flush_print(f"  sampled U S vs A V: {err:.2e} of sigma_1")
+    assert err <= 1e-13
+
