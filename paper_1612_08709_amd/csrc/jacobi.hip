@@ -8,8 +8,9 @@
 // onto 16-lane DPP reductions.
 //
 // Layout: M and V column-major in the 160 KB local data share (n*n doubles each).
-// 1024 threads = 64 groups of 16 lanes; per round of the round-robin ("circle") ordering
-// the <= 50 disjoint column pairs go to distinct groups, and a barrier separates rounds.
+// 16-lane groups (64 of them for n > 64, 32 for n <= 64); per round of the round-robin
+// ("circle") ordering the <= 50 disjoint column pairs go to distinct groups, and a barrier
+// separates rounds.
 // A sweep is the n'-1 rounds (n' = n rounded up to even) that visit every pair once.
 // A pair is rotated when |m_p^T m_q| > tol sqrt(|m_p|^2 |m_q|^2), tol = sqrt(n) * eps;
 // iteration stops after the first sweep without rotations or at max_sweeps.
@@ -20,9 +21,10 @@
 
 namespace tsv {
 
-constexpr int JAC_THREADS = 1024;
-
-__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(
+// NT threads = NT / 16 lane groups, at least one per column pair of a round (n <= 2 NT / 16):
+// 1024 for n <= 128, 512 for n <= 64, where each round's barrier then spans 8 waves, not 16.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_jacobi(
     const double* __restrict__ M0, int ldm, int n, int transpose, double wp, int max_sweeps,
     int sign_fix, double* __restrict__ Uo, double* __restrict__ So, double* __restrict__ Vo,
     tssvd_info* __restrict__ info, const int* __restrict__ gate,
@@ -40,7 +42,7 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(
   const int lane16 = tid & 15, grp = tid >> 4;
 
   // load (M column c, row i) = M0[i][c], or M0[c][i] for the transposed input
-  for (int idx = tid; idx < n * n; idx += JAC_THREADS) {
+  for (int idx = tid; idx < n * n; idx += NT) {
     const int c = idx / n, i = idx - c * n;
     M[idx] = transpose ? M0[c * ldm + i] : M0[i * ldm + c];
     V[idx] = (c == i) ? 1.0 : 0.0;
@@ -55,7 +57,11 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(
       const int j = tid;
       const double djj = dsrc ? dsrc[j * ldd + j] : M[j * n + j];
       if (fabs(djj) < thr) {
-        for (int c = 0; c < n; ++c) M[c * n + j] = 0.0;
+        // row j of the factor: a row of M, or a column of M when M is the transpose
+        if (transpose)
+          for (int i = 0; i < n; ++i) M[j * n + i] = 0.0;
+        else
+          for (int c = 0; c < n; ++c) M[c * n + j] = 0.0;
         atomicSub(&s_rank, 1);
       }
     }
@@ -131,12 +137,14 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(
     __syncthreads();
   }
 
-  // singular values = column norms; sign of each pair from w^T v_j
-  for (int c = grp; c < n; c += JAC_THREADS / 16) {
+  // singular values = column norms; sign of each pair from w^T v_j, v_j the right singular
+  // vector of the factor: column j of V, or of M (normalized) when M is the transpose
+  const double* sref = transpose ? M : V;
+  for (int c = grp; c < n; c += NT / 16) {
     double s2 = 0.0, sw = 0.0;
     for (int i = lane16; i < n; i += 16) {
       s2 = fma(M[c * n + i], M[c * n + i], s2);
-      sw = fma(sign_ref(i), V[c * n + i], sw);
+      sw = fma(sign_ref(i), sref[c * n + i], sw);
     }
     s2 = sum16(s2);
     sw = sum16(sw);
@@ -158,7 +166,7 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(
   }
   __syncthreads();
   const int rank = s_rank;
-  for (int idx = tid; idx < n * n; idx += JAC_THREADS) {
+  for (int idx = tid; idx < n * n; idx += NT) {
     const int c = idx / n, i = idx - c * n;
     const int pos = s_pos[c];
     const double sg = s_sig[c];
@@ -185,12 +193,21 @@ hipError_t jacobi_svd(const double* M, int ldm, int n, int transpose, double wp,
   const size_t lds = (size_t)2 * n * n * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)(2 * TSSVD_N_MAX * TSSVD_N_MAX * sizeof(double)));
+    const int mx = (int)(2 * TSSVD_N_MAX * TSSVD_N_MAX * sizeof(double));
+    hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<1024>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_jacobi<512>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(JAC_THREADS), lds, s, M, ldm, n, transpose, wp,
-                     max_sweeps, sign_fix, Uo, So, Vo, info, gate, dsrc, ldd);
+  if (n <= 64)
+    hipLaunchKernelGGL(k_jacobi<512>, dim3(1), dim3(512), lds, s, M, ldm, n, transpose, wp,
+                       max_sweeps, sign_fix, Uo, So, Vo, info, gate, dsrc, ldd);
+  else
+    hipLaunchKernelGGL(k_jacobi<1024>, dim3(1), dim3(1024), lds, s, M, ldm, n, transpose, wp,
+                       max_sweeps, sign_fix, Uo, So, Vo, info, gate, dsrc, ldd);
   return hipGetLastError();
 }
 
