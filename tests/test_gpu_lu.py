@@ -54,6 +54,23 @@ def test_lu_lowrank_vs_oracle(m, n, k, l, q):
     assert np.all(np.diff(S) <= 0)
 
 
+@pytest.mark.parametrize("m,n,k,l,q", [(5000, 400, 64, 64, 1), (1000, 50, 1, 1, 2)])
+def test_lu_width_limits(m, n, k, l, q):
+    """l = 64 (the widest register row, k = l) and l = 1 (one pivot per group).  With k = l
+    the trailing triplets sit at the edge of the sketch: rounding in the tracked subspaces
+    moves every sigma_j by O(eps sigma_1), so all are bounded absolutely (1e-13 sigma_1) and
+    the leading half relatively."""
+    flush_print("case lu limits", m, n, k, l, q)
+    A, _ = _planted(m, n, 540 + l, r=min(m, n, 300))
+    Om = sm.sketch(n, l, 540 + l)
+    U, S, V, _ = _lowrank(A, Om, k, q)
+    Ur, Sr, Vr = lowrank_ref(A, Om, k, q, tracking="lu")
+    h = k // 2 + 1
+    assert np.max(np.abs(S - Sr)) <= 1e-13 * Sr[0] and sigma_rel(S[:h], Sr[:h]) < 1e-11
+    assert np.max(col_sin(U[:, :h], Ur[:, :h])) < 1e-8
+    assert checks.ortho_spec(U) < 1e-13 and checks.ortho_spec(V) < 1e-13
+
+
 def test_lu_tracking_matches_qr_tracking_on_gpu():
     """Same column spaces: the LU route and the default route agree to rounding."""
     A, _ = _planted(30000, 1000, 531, r=400)

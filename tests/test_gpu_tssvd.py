@@ -104,6 +104,21 @@ def test_discard_rule_matches_oracle():
     assert checks.ortho_spec(U, r) < 1e-13
 
 
+@pytest.mark.parametrize("n,kept", [(80, 70), (64, 50)])
+def test_discard_rule_wide_factors(n, kept):
+    """The discard rule on the transposed Jacobi input at both kernel widths (n = 80: 64
+    lane groups; n = 64: 32): `kept` planted values from 1 to 1e-5, the rest 1e-15."""
+    sigma = np.concatenate([np.logspace(0, -5, kept), np.full(n - kept, 1e-15)])
+    A = sm.planted(4000, n, sigma, workload=42 + n)
+    U, S, V, info = _run(A, working_precision=1e-11)
+    Ur, Sr, Vr, r = tssvd_ref(A, wp=1e-11, double=False)
+    assert info["rank"] == r == kept
+    assert sigma_rel(S[:r], Sr[:r]) < 1e-11
+    assert np.max(col_sin(U[:, :r], Ur[:, :r])) < 1e-6 and np.max(col_sin(V[:, :r], Vr[:, :r])) < 1e-6
+    assert np.all(S[r:] == 0) and np.all(U[:, r:] == 0) and np.all(V[:, r:] == 0)
+    assert checks.ortho_spec(U, r) < 1e-13
+
+
 def test_deterministic_bitwise():
     A = _graded(50000, 48, seed=11)
     a = _run(A)
