@@ -28,4 +28,4 @@ from .gram_ref import gram_svd_ref, lowrank_gram_ref  # noqa: F401
 from .lowrank_ref import lowrank_ref  # noqa: F401
 from .lu_ref import lu_basis, lu_factor_gepp  # noqa: F401
 from .signs import sign_reference, apply_sign_rule  # noqa: F401
-from .tssvd_ref import discard_rule, tssvd_ref, tsqr_ref  # noqa: F401
+from .tssvd_ref import discard_rule, haar_mix, tssvd_ref, tsqr_ref  # noqa: F401

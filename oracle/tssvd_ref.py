@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from .philox import philox_normal
 from .signs import apply_sign_rule
 
 
@@ -34,6 +35,18 @@ def discard_rule(R: np.ndarray, wp: float) -> np.ndarray:
     if wp <= 0.0 or d.size == 0:
         return np.arange(R.shape[0])
     return np.nonzero(~(d < wp * d[0]))[0]
+
+
+def haar_mix(n: int, seed: int) -> np.ndarray:
+    """The n x n random orthogonal mixing Omega of Algorithm 1 step (1) (Remark on randomness):
+    Omega = Q diag(sign(diag R)) for the QR factorization G = Q R of an n x n matrix G of
+    Philox4x32-10 standard normals keyed by ``seed`` (``oracle.philox`` layout), which is
+    Haar-distributed.  The paper's own D F S D~ F S~ is a fast stand-in for such a matrix;
+    only its orthogonality and randomness enter the method.
+    """
+    G = philox_normal(n, n, seed)
+    Q, R = np.linalg.qr(G)
+    return Q * np.sign(np.diag(R))
 
 
 def tsqr_ref(Y: np.ndarray, wp: float = 0.0, mix: np.ndarray | None = None):

@@ -15,7 +15,7 @@ from oracle import checks, grad_ref, philox
 from oracle.gram_ref import alg3, alg4, gram_svd_ref, lowrank_gram_ref
 from oracle.lowrank_ref import lowrank_ref
 from oracle.lu_ref import lu_basis, lu_factor_gepp
-from oracle.tssvd_ref import discard_rule, tssvd_ref, tsqr_ref
+from oracle.tssvd_ref import discard_rule, haar_mix, tssvd_ref, tsqr_ref
 from synth import matrices as sm
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -92,6 +92,30 @@ def test_discard_rule_reading():
     R = np.diag([-2.0, 1e-3, -2e-11, 2e-11 * (1 - 1e-15), 5.0])
     np.testing.assert_array_equal(discard_rule(R, 1e-11), [0, 1, 2, 4])
     np.testing.assert_array_equal(discard_rule(R, 0.0), [0, 1, 2, 3, 4])
+
+
+def test_haar_mix_is_the_sign_fixed_q_of_the_philox_gaussian():
+    """Omega is orthogonal, and Omega^T G (G the Philox normals) is upper triangular with a
+    positive diagonal: the QR definition with the sign correction that makes Q Haar."""
+    n, seed = 17, 1234
+    Om = haar_mix(n, seed)
+    G = philox.philox_normal(n, n, seed)
+    assert np.abs(Om.T @ Om - np.eye(n)).max() < 1e-14
+    Rg = Om.T @ G
+    assert np.abs(np.tril(Rg, -1)).max() < 1e-13 * np.abs(Rg).max()
+    assert np.all(np.diag(Rg) > 0)
+
+
+@pytest.mark.parametrize("double", [False, True])
+def test_mixing_leaves_the_svd_unchanged(double):
+    """wp = 0: A Omega^T = Q R, R = U~ S V~^T, V = Omega^T V~ is still the SVD of A."""
+    A = sm.planted(500, 9, np.logspace(0, -3, 9), workload=44)
+    Om = haar_mix(9, 77)
+    U0, s0, V0, _ = tssvd_ref(A, double=double)
+    U1, s1, V1, _ = tssvd_ref(A, double=double, mix=Om)
+    np.testing.assert_allclose(s1, s0, rtol=1e-13)
+    np.testing.assert_allclose(U1, U0, atol=1e-12)
+    np.testing.assert_allclose(V1, V0, atol=1e-12)
 
 
 def test_tssvd_discard_rank_from_planted_gap():
