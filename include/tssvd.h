@@ -117,6 +117,16 @@ typedef struct {
  * otherwise); TSSVD_FLAG_GRAM with it is TSSVD_E_INVALID_ARG.  Other entry points ignore
  * the flag, except lowrank_svd_backward, which rejects it. */
 #define TSSVD_FLAG_LU 8
+/* tssvd: Algorithm 1 step (1), the random orthogonal mixing of the Remark on randomness,
+ * which makes the discard rule (working_precision > 0) reveal the rank whatever the order
+ * of A's columns.  Omega (n x n) is the Q factor of an n x n matrix of Philox4x32-10
+ * normals keyed by opts->seed (the lowrank_svd sketch layout), with the column signs that
+ * make diag(R) positive (Haar-distributed).  It is applied to the triangular factor:
+ * A = Q0 R0, R0 Omega^T = Q1 R', so A Omega^T = (Q0 Q1) R'; the rule reads the diagonal of
+ * R', V = Omega^T V~, U = Q0 Q1 U~.  The second pass of Algorithm 2 is unmixed.  With
+ * TSSVD_FLAG_GRAM it is TSSVD_E_INVALID_ARG; lowrank_svd and lowrank_svd_backward reject
+ * it (TSSVD_E_UNSUPPORTED). */
+#define TSSVD_FLAG_MIX 16
 
 /* Device-side record written (when non-NULL) at the end of every call. */
 typedef struct {

@@ -19,12 +19,12 @@ import torch
 from . import _native as N
 from ._native import (F32, F64, ORTHO_AUTO, ORTHO_ONCE, ORTHO_TWICE, PREC_FP64,  # noqa: F401
                       PREC_MIXED, TSSVD_N_MAX, TSSVD_TSQR_N_MAX, FLAG_F32_MFMA_FINAL,
-                      FLAG_NO_A_COPY, FLAG_GRAM, FLAG_LU)
+                      FLAG_NO_A_COPY, FLAG_GRAM, FLAG_LU, FLAG_MIX)
 
 __all__ = ["tsqr", "tssvd", "lowrank_svd", "lowrank_svd_backward", "LowRankSVD", "make_opts",
            "PREC_FP64", "PREC_MIXED", "ORTHO_AUTO", "ORTHO_ONCE", "ORTHO_TWICE",
            "FLAG_F32_MFMA_FINAL", "FLAG_NO_A_COPY", "FLAG_GRAM",
-           "FLAG_LU"]
+           "FLAG_LU", "FLAG_MIX"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:

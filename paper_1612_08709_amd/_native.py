@@ -23,6 +23,7 @@ FLAG_F32_MFMA_FINAL = 1
 FLAG_NO_A_COPY = 2
 FLAG_GRAM = 4
 FLAG_LU = 8
+FLAG_MIX = 16
 
 # every exported symbol declared in include/tssvd.h
 EXPORTS = (

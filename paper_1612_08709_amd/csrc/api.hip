@@ -410,8 +410,32 @@ __global__ void k_small_gemm(const double* __restrict__ A, const double* __restr
   C[i] = s;
 }
 
+// C = op(A) op(B) for n x n row-major matrices, op = transpose when ta / tb is set.
+__global__ void k_small_mm(const double* __restrict__ A, int ta, const double* __restrict__ B,
+                           int tb, int n, double* __restrict__ C) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * n) return;
+  const int r = i / n, c = i - r * n;
+  double s = 0.0;
+  for (int t = 0; t < n; ++t)
+    s = fma(ta ? A[t * n + r] : A[r * n + t], tb ? B[c * n + t] : B[t * n + c], s);
+  C[i] = s;
+}
+
+// Omega = Q diag(sign(diag R)) for G = Q R (n x n, row-major; R the TSQR root): the Q factor
+// of a Gaussian matrix with the sign correction that makes it Haar-distributed.
+__global__ void k_haar_fix(const double* __restrict__ Q, const double* __restrict__ R, int n,
+                           double* __restrict__ Om) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * n) return;
+  const int c = i % n;
+  Om[i] = R[c * n + c] < 0.0 ? -Q[i] : Q[i];
+}
+
 struct TssvdWs {
   TsqrPlan p;
+  TsqrPlan pn;                     // mixing: QR factorizations of n x n matrices
+  double *Om, *Mm, *Mu, *Mv;       // mixing: Omega, R Omega^T, and the small SVD's factors
   double *Ut, *S, *Vt, *T, *P2, *S2, *W2, *V2, *G, *part, *ortho;
   double *gnrm, *gnrm2, *gscale;  // Gram route: norms of the two passes, column scales
   int* gate;
@@ -424,7 +448,13 @@ TssvdWs tssvd_layout(int64_t m, int n, void* work) {
   Carver c(work);
   w.p = tsqr_plan(m, n);
   tsqr_carve(w.p, c);
+  w.pn = tsqr_plan(n, n);
+  tsqr_carve(w.pn, c);
   const size_t nn = (size_t)n * n;
+  w.Om = c.take<double>(nn);
+  w.Mm = c.take<double>(nn);
+  w.Mu = c.take<double>(nn);
+  w.Mv = c.take<double>(nn);
   w.Ut = c.take<double>(nn);
   w.S = c.take<double>(n);
   w.Vt = c.take<double>(nn);
@@ -587,6 +617,8 @@ int tssvd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, dou
   if (!work || work_bytes < w.bytes) return TSSVD_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
 
+  const bool mix = (o.flags & TSSVD_FLAG_MIX) != 0;
+  if (mix && (o.flags & TSSVD_FLAG_GRAM)) return TSSVD_E_INVALID_ARG;
   TRY(info_init(info, s));
   if (o.flags & TSSVD_FLAG_GRAM)
     return hip_status(tssvd_gram(A, a_dtype, m, ni, lda, U, ldu, S, V, ldv, info, w, o, s));
@@ -595,8 +627,29 @@ int tssvd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, dou
   // whose columns converge in about half the sweeps that R's need when R's columns are
   // mixed (measured 10 vs 23 sweeps for n = 100, sigma from 1 to 1e-6).
   TRY(tsqr_factor(w.p, A, a_dtype, lda, s, true));
-  TRY(jacobi_svd(tsqr_root(w.p), ni, ni, 1, o.working_precision, o.max_jacobi_sweeps, 1, w.Vt,
-                 w.S, w.Ut, info, s));
+  const unsigned nb = (unsigned)((ni * ni + 255) / 256);
+  if (!mix) {
+    TRY(jacobi_svd(tsqr_root(w.p), ni, ni, 1, o.working_precision, o.max_jacobi_sweeps, 1,
+                   w.Vt, w.S, w.Ut, info, s));
+  } else {
+    // Step (1) with the mixing moved onto R: A = Q0 R0 and R0 Omega^T = Q1 R' give
+    // A Omega^T = (Q0 Q1) R', the factorization of the mixed matrix, at O(n^3) instead of a
+    // pass over A.  Omega is the sign-corrected Q of an n x n Philox Gaussian (Haar).  The
+    // discard rule then reads the diagonal of R'; V = Omega^T V~ and U = Q0 (Q1 U~).
+    TRY(philox_sketch(w.Om, n, ni, o.seed, s));                       // G
+    TRY(tsqr_factor(w.pn, w.Om, TSSVD_F64, n, s));                     // G = QG RG
+    TRY(fill_identity(w.Mv, ni, ni, s));
+    TRY(tsqr_apply(w.pn, w.Mv, ni, w.Mu, n, s));                       // QG
+    hipLaunchKernelGGL(k_haar_fix, dim3(nb), dim3(256), 0, s, w.Mu, tsqr_root(w.pn), ni, w.Om);
+    hipLaunchKernelGGL(k_small_mm, dim3(nb), dim3(256), 0, s, tsqr_root(w.p), 0, w.Om, 1, ni,
+                       w.Mm);                                          // R0 Omega^T
+    TRY(tsqr_factor(w.pn, w.Mm, TSSVD_F64, n, s));                     // = Q1 R'
+    TRY(jacobi_svd(tsqr_root(w.pn), ni, ni, 1, o.working_precision, o.max_jacobi_sweeps, 0,
+                   w.Mv, w.S, w.Mu, info, s));                         // R' = U~ S V~^T
+    hipLaunchKernelGGL(k_small_mm, dim3(nb), dim3(256), 0, s, w.Om, 1, w.Mv, 0, ni, w.Vt);
+    TRY(tsqr_apply(w.pn, w.Mu, ni, w.Ut, n, s));                       // Q1 U~
+    TRY(sign_fix_cols(w.Vt, n, ni, ni, w.Ut, ni, ni, s));
+  }
   TRY(tsqr_apply(w.p, w.Ut, ni, U, ldu, s, true));
   TRY(copy_matrix(w.S, 1, ni, ni, S, ni, s));
   TRY(copy_matrix(w.Vt, n, ni, n, V, ldv, s));
@@ -848,6 +901,7 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   const bool lu = (o.flags & TSSVD_FLAG_LU) != 0;
   const double wp = o.working_precision;  // > 0: the paper's discard rule (rank-deficient mode)
   if (lu && gram) return TSSVD_E_INVALID_ARG;
+  if (o.flags & TSSVD_FLAG_MIX) return TSSVD_E_UNSUPPORTED;
   if (lu && (wp > 0.0 || l > LU_L_MAX)) return TSSVD_E_UNSUPPORTED;
   const int ki = (int)k, li = (int)l;
   const bool acopy = mixed && q >= 1 && !(o.flags & TSSVD_FLAG_NO_A_COPY);
@@ -1066,7 +1120,7 @@ int lowrank_svd_backward(const void* A, int32_t a_dtype, int64_t m, int64_t n, i
   const tssvd_opts o = resolve(opts);
   if (check_opts(o) != TSSVD_OK) return TSSVD_E_INVALID_ARG;
   if (o.prec != TSSVD_PREC_FP64 || o.working_precision > 0.0 ||
-      (o.flags & (TSSVD_FLAG_GRAM | TSSVD_FLAG_LU)))
+      (o.flags & (TSSVD_FLAG_GRAM | TSSVD_FLAG_LU | TSSVD_FLAG_MIX)))
     return TSSVD_E_UNSUPPORTED;
   (void)U; (void)S; (void)V;  // the forward is recomputed from (A, Omega); see the header
   const int ki = (int)k, li = (int)l, qi = (int)q;

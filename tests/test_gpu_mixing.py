@@ -1,0 +1,82 @@
+"""GPU parity of the random mixing of Algorithm 1 step (1) (TSSVD_FLAG_MIX) through the C
+ABI vs the CPU oracle with the same mixing matrix: the oracle rebuilds Omega from its own
+Philox4x32-10 normals (``oracle.haar_mix``), the library draws it on the device from the
+same counter-based generator and seed."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import checks
+from oracle.tssvd_ref import haar_mix, tssvd_ref
+from synth import matrices as sm
+
+from gpu_util import col_sin, dev, flush_print, host, sigma_rel
+
+pytestmark = pytest.mark.gpu
+
+T = pytest.importorskip("paper_1612_08709_amd")
+
+
+def _run(A, **kw):
+    U, S, V, info = T.tssvd(dev(A), **kw)
+    torch.cuda.synchronize()
+    return host(U), host(S), host(V), info
+
+
+@pytest.mark.parametrize("m,n", [(300, 5), (3000, 33), (5000, 64), (4099, 100)])
+@pytest.mark.parametrize("ortho", [T.ORTHO_ONCE, T.ORTHO_TWICE])
+def test_mixing_without_discard_matches_oracle_and_unmixed(m, n, ortho):
+    flush_print("case mix", m, n, ortho)
+    A = sm.planted(m, n, np.logspace(0, -4, n), workload=600 + n)
+    seed = 9000 + n
+    U, S, V, info = _run(A, flags=T.FLAG_MIX, seed=seed, ortho=ortho)
+    Ur, Sr, Vr, r = tssvd_ref(A, double=(ortho != T.ORTHO_ONCE), mix=haar_mix(n, seed))
+    Uu, Su, Vu, _ = _run(A, ortho=ortho)
+    assert info["rank"] == n == r
+    assert sigma_rel(S, Sr) < 1e-12 and sigma_rel(S, Su) < 1e-12
+    assert np.max(col_sin(U, Ur)) < 1e-9 and np.max(col_sin(V, Vr)) < 1e-9
+    np.testing.assert_allclose(U, Ur, atol=1e-9)
+    np.testing.assert_allclose(V, Vr, atol=1e-9)
+    np.testing.assert_allclose(V, Vu, atol=1e-9)
+    assert checks.ortho_spec(U) < 1e-13 and checks.ortho_spec(V) < 1e-13
+
+
+@pytest.mark.parametrize("ortho", [T.ORTHO_ONCE, T.ORTHO_TWICE])
+def test_mixing_with_discard_matches_oracle(ortho):
+    """sigma: 12 values from 1 to 1e-5, then 8 at 1e-15; wp = 1e-11 keeps 12 on both sides."""
+    n = 20
+    sigma = np.concatenate([np.logspace(0, -5, 12), np.full(8, 1e-15)])
+    A = sm.planted(3000, n, sigma, workload=620)
+    U, S, V, info = _run(A, flags=T.FLAG_MIX, seed=31, ortho=ortho, working_precision=1e-11)
+    Ur, Sr, Vr, r = tssvd_ref(A, wp=1e-11, double=(ortho != T.ORTHO_ONCE), mix=haar_mix(n, 31))
+    assert info["rank"] == r == 12
+    assert sigma_rel(S[:r], Sr[:r]) < 1e-10
+    assert np.max(col_sin(U[:, :r], Ur[:, :r])) < 1e-6
+    assert np.max(col_sin(V[:, :r], Vr[:, :r])) < 1e-6
+    assert np.all(S[r:] == 0) and np.all(U[:, r:] == 0) and np.all(V[:, r:] == 0)
+
+
+def test_mixing_reveals_a_rank_the_unmixed_rule_misses():
+    """A zero first column makes R_11 = 0, so |R_jj| < wp |R_11| never holds and nothing
+    is dropped without mixing; mixed, the rule drops the zero direction (rank n - 1), as the
+    oracle with the same Omega does."""
+    n = 16
+    A = sm.planted(2000, n, np.logspace(0, -3, n), workload=621)
+    A[:, 0] = 0.0
+    Uu, Su, Vu, iu = _run(A, working_precision=1e-11, ortho=T.ORTHO_ONCE)
+    U, S, V, info = _run(A, flags=T.FLAG_MIX, seed=5, working_precision=1e-11,
+                         ortho=T.ORTHO_ONCE)
+    Ur, Sr, Vr, r = tssvd_ref(A, wp=1e-11, double=False, mix=haar_mix(n, 5))
+    assert iu["rank"] == n
+    assert info["rank"] == r == n - 1
+    assert sigma_rel(S[:r], Sr[:r]) < 1e-12
+    assert S[n - 1] == 0.0 and np.all(U[:, n - 1] == 0) and np.all(V[:, n - 1] == 0)
+    assert np.max(col_sin(V[:, :r], Vr[:, :r])) < 1e-9
+
+
+def test_mixing_flag_argument_errors():
+    A = dev(np.ones((300, 40)))
+    with pytest.raises(ValueError):
+        T.tssvd(A, flags=T.FLAG_MIX | T.FLAG_GRAM)
+    with pytest.raises(ValueError):
+        T.lowrank_svd(A, 5, 10, 1, dev(sm.sketch(40, 10, 622)), flags=T.FLAG_MIX)
