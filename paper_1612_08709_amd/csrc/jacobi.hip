@@ -23,7 +23,7 @@ namespace tsv {
 
 // NT threads = NT / 16 lane groups, at least one per column pair of a round (n <= 2 NT / 16):
 // 1024 for n <= 128, 512 for n <= 64, where each round's barrier then spans 8 waves, not 16.
-template <int NT>
+template <int NT, int NPL = (2 * NT / 16 + 15) / 16>  // NPL: entries per lane, n <= 16 NPL
 __global__ __launch_bounds__(NT) void k_jacobi(
     const double* __restrict__ M0, int ldm, int n, int transpose, double wp, int max_sweeps,
     int sign_fix, double* __restrict__ Uo, double* __restrict__ So, double* __restrict__ Vo,
@@ -95,9 +95,15 @@ __global__ __launch_bounds__(NT) void k_jacobi(
         if (q < n) {
           double* mp = M + p * n;
           double* mq = M + q * n;
+          // the pair's entries stay in registers from the dot products to the rotation
+          double xr[NPL], yr[NPL];
           double al = 0.0, be = 0.0, ga = 0.0;
-          for (int i = lane16; i < n; i += 16) {
-            const double x = mp[i], y = mq[i];
+#pragma unroll
+          for (int k = 0; k < NPL; ++k) {
+            const int i = lane16 + 16 * k;
+            const double x = (i < n) ? mp[i] : 0.0, y = (i < n) ? mq[i] : 0.0;
+            xr[k] = x;
+            yr[k] = y;
             al = fma(x, x, al);
             be = fma(y, y, be);
             ga = fma(x, y, ga);
@@ -114,17 +120,18 @@ __global__ __launch_bounds__(NT) void k_jacobi(
             const double tt = (d >= 0.0 ? g2 : -g2) / (fabs(d) + sqrt(fma(d, d, g2 * g2)));
             const double c = rsqrt(fma(tt, tt, 1.0));
             const double s = c * tt;
-            for (int i = lane16; i < n; i += 16) {
-              const double x = mp[i], y = mq[i];
-              mp[i] = fma(c, x, -s * y);
-              mq[i] = fma(s, x, c * y);
-            }
             double* vp = V + p * n;
             double* vq = V + q * n;
-            for (int i = lane16; i < n; i += 16) {
-              const double x = vp[i], y = vq[i];
-              vp[i] = fma(c, x, -s * y);
-              vq[i] = fma(s, x, c * y);
+#pragma unroll
+            for (int k = 0; k < NPL; ++k) {
+              const int i = lane16 + 16 * k;
+              if (i < n) {
+                const double vx = vp[i], vy = vq[i];
+                mp[i] = fma(c, xr[k], -s * yr[k]);
+                mq[i] = fma(s, xr[k], c * yr[k]);
+                vp[i] = fma(c, vx, -s * vy);
+                vq[i] = fma(s, vx, c * vy);
+              }
             }
             if (lane16 == 0) s_rot = 1;
           }
