@@ -210,8 +210,8 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
  * l, q and options; they are not read.  2q+2 passes over A recompute the forward, 2q+1
  * passes and one m x (2q+2)l x n product form gA.
  *   gA : m x n, a_dtype, stride ldga (written)
- * Requires opts->prec == TSSVD_PREC_FP64, working_precision <= 0 and neither
- * TSSVD_FLAG_GRAM nor TSSVD_FLAG_LU (TSSVD_E_UNSUPPORTED otherwise).
+ * Requires opts->prec == TSSVD_PREC_FP64, working_precision <= 0 and none of
+ * TSSVD_FLAG_GRAM, TSSVD_FLAG_LU, TSSVD_FLAG_MIX (TSSVD_E_UNSUPPORTED otherwise).
  * ------------------------------------------------------------------------------------- */
 int lowrank_svd_backward_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t l,
                                          int64_t q, int32_t a_dtype, const tssvd_opts* opts,

@@ -127,3 +127,44 @@ def test_python_layer_fails_loudly_without_gpu_tensors(native):
     import paper_1612_08709_amd as T
     with pytest.raises(ValueError):
         T.tssvd(torch.zeros(10, 3, dtype=torch.float64))
+
+
+def _header_constants():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    consts = {k: int(v) for k, v in re.findall(r"#define\s+TSSVD_(\w+)\s+(\d+)", text)}
+    consts.update({k: int(v) for k, v in re.findall(r"\bTSSVD_(\w+)\s*=\s*(\d+)", text)})
+    return consts
+
+
+def _header_struct_fields(name):
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    body = re.search(r"typedef struct\s*\{([^}]*)\}\s*" + name + ";", text).group(1)
+    return [re.findall(r"(\w+)\s*;", d)[0] for d in body.split(";") if d.strip()
+            for d in [d + ";"]]
+
+
+def test_python_constants_match_the_header():
+    """Every flag, status, dtype, precision and ortho code the binding hard-codes is the
+    header's value."""
+    from paper_1612_08709_amd import _native as N
+    h = _header_constants()
+    pairs = {"FLAG_F32_MFMA_FINAL": N.FLAG_F32_MFMA_FINAL, "FLAG_NO_A_COPY": N.FLAG_NO_A_COPY,
+             "FLAG_GRAM": N.FLAG_GRAM, "FLAG_LU": N.FLAG_LU, "FLAG_MIX": N.FLAG_MIX,
+             "N_MAX": N.TSSVD_N_MAX, "TSQR_N_MAX": N.TSSVD_TSQR_N_MAX, "OK": N.OK,
+             "E_INVALID_ARG": N.E_INVALID_ARG, "E_WORKSPACE": N.E_WORKSPACE, "E_HIP": N.E_HIP,
+             "E_UNSUPPORTED": N.E_UNSUPPORTED, "F64": N.F64, "F32": N.F32,
+             "PREC_FP64": N.PREC_FP64, "PREC_MIXED": N.PREC_MIXED, "ORTHO_AUTO": N.ORTHO_AUTO,
+             "ORTHO_ONCE": N.ORTHO_ONCE, "ORTHO_TWICE": N.ORTHO_TWICE}
+    for k, v in pairs.items():
+        assert h[k] == v, k
+    flags = [v for k, v in h.items() if k.startswith("FLAG_")]
+    assert len(set(flags)) == len(flags) and all(f & (f - 1) == 0 for f in flags)
+
+
+def test_python_structs_match_the_header():
+    """ctypes mirrors of tssvd_opts and tssvd_info: same fields in the same order."""
+    from paper_1612_08709_amd import _native as N
+    assert [f for f, _ in N.Opts._fields_] == _header_struct_fields("tssvd_opts")
+    assert [f for f, _ in N.Info._fields_] == _header_struct_fields("tssvd_info")
