@@ -157,6 +157,10 @@ def test_python_constants_match_the_header():
              "E_UNSUPPORTED": N.E_UNSUPPORTED, "F64": N.F64, "F32": N.F32,
              "PREC_FP64": N.PREC_FP64, "PREC_MIXED": N.PREC_MIXED, "ORTHO_AUTO": N.ORTHO_AUTO,
              "ORTHO_ONCE": N.ORTHO_ONCE, "ORTHO_TWICE": N.ORTHO_TWICE}
+    pairs.update({k: getattr(N, k) for k in ("PROF_AX", "PROF_ATQ", "PROF_LEAF_FACTOR",
+                                             "PROF_LEAF_APPLY", "PROF_AX_BF16", "PROF_ATQ_BF16",
+                                             "PROF_AX_FINAL", "PROF_ATQ_FINAL", "PROF_AX_BF16C",
+                                             "PROF_ATQ_BF16C")})
     for k, v in pairs.items():
         assert h[k] == v, k
     flags = [v for k, v in h.items() if k.startswith("FLAG_")]
