@@ -41,6 +41,20 @@ def test_mixing_without_discard_matches_oracle_and_unmixed(m, n, ortho):
     assert checks.ortho_spec(U) < 1e-13 and checks.ortho_spec(V) < 1e-13
 
 
+def test_mixing_float32_storage_auto_mode():
+    """float32 A (read exactly), default AUTO second pass: the oracle on the upcast matrix."""
+    n = 40
+    A32 = sm.planted(6000, n, np.logspace(0, -3, n), workload=623).astype(np.float32)
+    U, S, V, info = T.tssvd(dev(A32), flags=T.FLAG_MIX, seed=17)
+    torch.cuda.synchronize()
+    U, S, V = host(U), host(S), host(V)
+    Ur, Sr, Vr, r = tssvd_ref(A32.astype(np.float64), double=True, mix=haar_mix(n, 17))
+    assert info["rank"] == n == r
+    assert sigma_rel(S, Sr) < 1e-12
+    assert np.max(col_sin(U, Ur)) < 1e-9 and np.max(col_sin(V, Vr)) < 1e-9
+    assert checks.ortho_spec(U) < 1e-13
+
+
 @pytest.mark.parametrize("ortho", [T.ORTHO_ONCE, T.ORTHO_TWICE])
 def test_mixing_with_discard_matches_oracle(ortho):
     """sigma: 12 values from 1 to 1e-5, then 8 at 1e-15; wp = 1e-11 keeps 12 on both sides."""
