@@ -129,7 +129,7 @@ def staircase(k: int) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------------------------
-# Workloads.  Sizes follow the tall-skinny and randomized low-rank experiments; see the design doc.
+# Workloads.  Sizes follow the tall-skinny and randomized low-rank experiments (Sections 2 and 3).
 # --------------------------------------------------------------------------------------------
 
 def workload_spec(w: int) -> dict:
