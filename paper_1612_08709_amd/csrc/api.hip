@@ -7,6 +7,8 @@
 #include "common.h"
 #include "internal.h"
 
+#include <climits>
+
 using namespace tsv;
 
 namespace {
@@ -902,7 +904,9 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   const double wp = o.working_precision;  // > 0: the paper's discard rule (rank-deficient mode)
   if (lu && gram) return TSSVD_E_INVALID_ARG;
   if (o.flags & TSSVD_FLAG_MIX) return TSSVD_E_UNSUPPORTED;
-  if (lu && (wp > 0.0 || l > LU_L_MAX)) return TSSVD_E_UNSUPPORTED;
+  // the tournament keeps row indices as int
+  if (lu && (wp > 0.0 || l > LU_L_MAX || m > INT_MAX - 1024 || n > INT_MAX - 1024))
+    return TSSVD_E_UNSUPPORTED;
   const int ki = (int)k, li = (int)l;
   const bool acopy = mixed && q >= 1 && !(o.flags & TSSVD_FLAG_NO_A_COPY);
   LowrankWs w = lowrank_layout(m, n, ki, li, work, mixed, acopy);

@@ -115,6 +115,31 @@ def test_calls_reject_bad_arguments_before_any_work(native):
                            fake, 16, C.byref(o), null) == N.E_WORKSPACE
 
 
+def test_route_flags_are_validated_on_the_host(native):
+    """Flag combinations the library does not take come back before any work is enqueued."""
+    lib, N = native.lib(), native
+    null = C.c_void_p(0)
+    fake = C.c_void_p(256)  # never dereferenced: validation fails first
+
+    def opts(flags, wp=0.0):
+        o = N.default_opts()
+        o.flags, o.working_precision = flags, wp
+        return o
+
+    def lowrank(o, m=100, n=50, l=8):
+        return lib.lowrank_svd(fake, N.F64, m, n, n, 4, l, 1, null, fake, 4, fake, fake, 4, null,
+                               fake, 1 << 40, C.byref(o), null)
+
+    assert lowrank(opts(N.FLAG_LU | N.FLAG_GRAM)) == N.E_INVALID_ARG
+    assert lowrank(opts(N.FLAG_LU, wp=1e-11)) == N.E_UNSUPPORTED
+    assert lowrank(opts(N.FLAG_LU), n=200, l=65) == N.E_UNSUPPORTED
+    assert lowrank(opts(N.FLAG_LU), m=1 << 31) == N.E_UNSUPPORTED
+    assert lowrank(opts(N.FLAG_MIX)) == N.E_UNSUPPORTED
+    o = opts(N.FLAG_MIX | N.FLAG_GRAM)
+    assert lib.tssvd(fake, N.F64, 100, 10, 10, fake, 10, fake, fake, 10, null, fake, 1 << 40,
+                     C.byref(o), null) == N.E_INVALID_ARG
+
+
 def test_sign_reference_constant_is_the_golden_ratio_conjugate():
     """The device source spells g = (sqrt(5)-1)/2 as a decimal literal; it must be that double."""
     src = open(os.path.join(ROOT, "paper_1612_08709_amd", "csrc", "common.h")).read()
