@@ -113,8 +113,8 @@ typedef struct {
  * picked rows competing again up a tree) instead of an orthonormal Q; they span the same
  * columns.  The last step keeps Algorithm 2's double orthonormalization, so the result is
  * that of Algorithm 7 up to rounding.  A singular pivot block falls back to the Householder
- * Q for that step.  Requires l <= 64 and working_precision <= 0 (TSSVD_E_UNSUPPORTED
- * otherwise); TSSVD_FLAG_GRAM with it is TSSVD_E_INVALID_ARG.  Other entry points ignore
+ * Q for that step.  Requires l <= 64, working_precision <= 0 and m, n < 2^31 - 1024
+ * (TSSVD_E_UNSUPPORTED otherwise); TSSVD_FLAG_GRAM with it is TSSVD_E_INVALID_ARG.  Other entry points ignore
  * the flag, except lowrank_svd_backward, which rejects it. */
 #define TSSVD_FLAG_LU 8
 /* tssvd: Algorithm 1 step (1), the random orthogonal mixing of the Remark on randomness,
