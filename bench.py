@@ -38,12 +38,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def ortho_gpu(U):
-    """||U^T U - I||_2 in float64 on the device (checker only, outside the timed region)."""
+def ortho_gpu(U, block=4096, group=256):
+    """||U^T U - I||_2 in float64 (checker only, outside the timed region).  The Gram is
+    summed pairwise over 4096-row blocks on the device, so its own rounding stays far below
+    1e-14 at millions of rows (a single long GEMM would not)."""
     import torch
-    G = U.T @ U
-    G -= torch.eye(G.shape[0], dtype=G.dtype, device=G.device)
-    return float(torch.linalg.matrix_norm(G, ord=2))
+    m, n = U.shape
+    parts = []
+    for g0 in range(0, m, block * group):
+        rows = min(m - g0, block * group)
+        nb = (rows + block - 1) // block
+        Ub = torch.zeros(nb * block, n, dtype=torch.float64, device=U.device)
+        Ub[:rows] = U[g0:g0 + rows]
+        Ub = Ub.view(nb, block, n)
+        parts.append(torch.bmm(Ub.transpose(1, 2).contiguous(), Ub))
+    G = torch.cat(parts)
+    while G.shape[0] > 1:
+        if G.shape[0] % 2:
+            G = torch.cat([G, torch.zeros_like(G[:1])])
+        G = G[0::2] + G[1::2]
+    G = G[0] - torch.eye(n, dtype=torch.float64, device=U.device)
+    return float(np.linalg.norm(G.cpu().numpy(), 2))
 
 
 def time_calls(fn, steps, warmup):
@@ -66,16 +81,21 @@ def time_calls(fn, steps, warmup):
 
 # per-kernel model: algorithmic bytes and flops of one launch, and the bound it is priced at
 def kernel_model(name, m, n, l, a_bytes_per_elem, a_copy=False):
-    """Algorithmic bytes and flops of one launch.  a_copy: the mixed power steps keep a
-    bfloat16 copy of A (written by the first pass, read by ax_bf16c / atq_bf16c)."""
+    """Algorithmic bytes and flops of one launch: the bytes the method itself must move in
+    that pass (A as the pass reads it, the small operand, the sketch written or read).
+    a_copy: the mixed power steps keep a bfloat16 copy of A, written by the first pass
+    (ax_bf16) and read by the later power-step passes (ax_bf16c / atq_bf16c).  Writing the
+    copy is not the method's work: it is reported as `copy_write_bytes`, never counted in
+    alg_bytes, and the copy-reading passes count the copy they stream."""
     L = 16 * ((l + 15) // 16)
     abytes = m * n * a_bytes_per_elem
-    cbytes = m * (32 * ((n + 31) // 32)) * 2  # the bfloat16 copy (columns padded to 32)
+    cbytes = m * (64 * ((n + 63) // 64)) * 2  # the bfloat16 copy (columns padded to 64)
     flops = 2.0 * m * n * l
     if name in ("gemm_ax_f64", "gemm_atq_f64"):
         return dict(alg_bytes=abytes + 8 * (m * l + n * l), flops=flops, dtype="f64")
     if name == "ax_bf16":
-        return dict(alg_bytes=abytes + (cbytes if a_copy else 0) + 2 * n * L + 8 * m * l,
+        return dict(alg_bytes=abytes + 2 * n * L + 8 * m * l,
+                    copy_write_bytes=cbytes if a_copy else 0,
                     flops=2.0 * m * n * L, dtype="bf16")
     if name == "atq_bf16":
         return dict(alg_bytes=abytes + 2 * m * L + 8 * n * l, flops=2.0 * m * n * L,
@@ -132,6 +152,10 @@ def run_lowrank(A, spec, prec, steps, warmup, workload, flags=0):
         if mod:
             d.update(alg_bytes=mod["alg_bytes"], gbs=round(mod["alg_bytes"] / avg / 1e9, 2),
                      tflops=round(mod["flops"] / avg / 1e12, 3), mfma_dtype=mod["dtype"])
+            if mod.get("copy_write_bytes"):
+                d.update(copy_write_bytes=mod["copy_write_bytes"],
+                         gbs_incl_copy_write=round((mod["alg_bytes"] + mod["copy_write_bytes"])
+                                                   / avg / 1e9, 2))
         kernels[name] = d
     return dict(sec=sec, value=passes * abytes / sec / 1e9, passes=passes, abytes=abytes,
                 ortho_u=ortho_gpu(U), ortho_v=ortho_gpu(V), kernels=kernels, Om=Om,
@@ -314,11 +338,17 @@ def roofline_of(kernels):
     ai = kd["tflops"] * 1e12 / (kd["gbs"] * 1e9)
     ridge = PEAK_TFLOPS[dt] * 1e12 / (HBM_PEAK_GBS * 1e9)
     if ai < ridge:
-        return {"bound": "hbm", "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4), "traffic": tr_bytes,
-                "traffic_detail": tr, "kernel": name,
-                "avg_ms": kd["avg_ms"], "launches": kd["launches"],
-                "alg_bytes_per_launch": kd["alg_bytes"]}
+        out = {"bound": "hbm", "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4), "traffic": tr_bytes,
+               "traffic_detail": tr, "kernel": name,
+               "avg_ms": kd["avg_ms"], "launches": kd["launches"],
+               "alg_bytes_per_launch": kd["alg_bytes"]}
+        if kd.get("copy_write_bytes"):
+            out["copy_write_bytes_per_launch"] = kd["copy_write_bytes"]
+            out["note"] = ("achieved counts the method's bytes only (A read, operand, sketch "
+                           "written); the bfloat16 copy of A this pass also writes is in "
+                           "copy_write_bytes_per_launch and in traffic, not in achieved")
+        return out
     return {"bound": "mfma", "achieved": kd["tflops"], "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
             "frac": round(kd["tflops"] / PEAK_TFLOPS[dt], 4), "traffic": tr_bytes,
             "traffic_detail": tr, "kernel": name,
@@ -348,13 +378,22 @@ def cpu_baseline_lowrank(A, Om, spec, rows):
                        f"{Ah.dtype}), all {passes} passes, one run")
 
 
-def leg_tssvd(workload, steps, warmup, dtype_name=None):
+def leg_tssvd(workload, steps, warmup, dtype_name=None, ortho=None, prec=None, A=None,
+              label=None):
+    """One tall-skinny SVD configuration, timed.  ortho defaults to AUTO (the second
+    orthonormalization runs when the device-measured ||U^T U - I||_F exceeds 1e-13), the
+    mode that meets the float64 orthonormality gate."""
     import torch
     import paper_1612_08709_amd as T
     from paper_1612_08709_amd import _native as N
-    spec, A = generate(workload, dtype_name)
+    if A is None:
+        spec, A = generate(workload, dtype_name)
+    else:
+        from synth import matrices as sm
+        spec = sm.workload_spec(workload)
     m, n = spec["m"], spec["n"]
-    o = T.make_opts(ortho=T.ORTHO_ONCE)
+    o = T.make_opts(ortho=T.ORTHO_AUTO if ortho is None else ortho,
+                    prec=T.PREC_FP64 if prec is None else prec)
     nb = C.c_size_t()
     lib = N.lib()
     code = N.F64 if A.dtype == torch.float64 else N.F32
@@ -363,28 +402,35 @@ def leg_tssvd(workload, steps, warmup, dtype_name=None):
     U = torch.empty(m, n, dtype=torch.float64, device="cuda:0")
     S = torch.empty(n, dtype=torch.float64, device="cuda:0")
     V = torch.empty(n, n, dtype=torch.float64, device="cuda:0")
+    info = torch.zeros(C.sizeof(N.Info), dtype=torch.uint8, device="cuda:0")
     stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
     def run():
         N.check(lib.tssvd(C.c_void_p(A.data_ptr()), code, m, n, n, C.c_void_p(U.data_ptr()), n,
-                          C.c_void_p(S.data_ptr()), C.c_void_p(V.data_ptr()), n, None,
-                          C.c_void_p(work.data_ptr()), nb.value, C.byref(o), stream), "tssvd")
+                          C.c_void_p(S.data_ptr()), C.c_void_p(V.data_ptr()), n,
+                          C.c_void_p(info.data_ptr()), C.c_void_p(work.data_ptr()), nb.value,
+                          C.byref(o), stream), "tssvd")
 
     sec, prof = time_calls(run, steps, warmup)
     torch.cuda.synchronize()
+    inf = N.Info.from_buffer_copy(bytes(info.cpu().numpy().tobytes()))
     sig = torch.tensor(spec["sigma"], device="cuda:0")
     srel = float(((S - sig).abs() / sig).max())
     abytes = m * n * A.element_size()
     lf = prof.get("tsqr_leaf_factor", (0.0, 1))
     la = prof.get("tsqr_leaf_apply", (0.0, 1))
     lf_s = lf[0] / lf[1] / 1e3
-    out = dict(workload=f"tall-skinny SVD {m} x {n} {str(A.dtype)[6:]}",
+    modes = {T.ORTHO_AUTO: "auto", T.ORTHO_ONCE: "once", T.ORTHO_TWICE: "twice"}
+    out = dict(workload=label or f"tall-skinny SVD {m} x {n} {str(A.dtype)[6:]}",
+               ortho_mode=modes[o.ortho], prec="mixed" if o.prec == T.PREC_MIXED else "fp64",
                ms_per_call=round(sec * 1e3, 4), gbs_A_per_call=round(abytes / sec / 1e9, 2),
-               ortho_U=ortho_gpu(U), sigma_rel_err_vs_planted=srel,
+               ortho_U=ortho_gpu(U), ortho_V=ortho_gpu(V),
+               second_pass_ran=int(inf.reorth), device_ortho_F_first_pass=inf.ortho,
+               sigma_rel_err_vs_planted=srel,
                leaf_factor_ms=round(lf[0] / lf[1], 4), leaf_apply_ms=round(la[0] / la[1], 4),
-               leaf_factor_gbs=round(abytes / lf_s / 1e9, 2),
-               leaf_factor_fp64_tflops=round(2.0 * m * n * n / lf_s / 1e12, 3))
-    del A, U, work
+               leaf_factor_gbs=round(abytes / lf_s / 1e9, 2) if lf[0] else None,
+               leaf_factor_fp64_tflops=round(2.0 * m * n * n / lf_s / 1e12, 3) if lf[0] else None)
+    del U, work
     torch.cuda.empty_cache()
     return out
 
@@ -499,11 +545,22 @@ def main():
             elif leg == "w5":
                 legs["w5"] = leg_backward(args.steps, args.warmup)
             elif leg == "w3":
-                legs["w3_f64"] = leg_tssvd(3, args.steps, args.warmup, "f64")
-                legs["w3_f32"] = leg_tssvd(3, args.steps, args.warmup, "f32")
+                _, A3 = generate(3, "f64")
+                legs["w3_f64"] = leg_tssvd(3, args.steps, args.warmup, A=A3)
+                legs["w3_f64_once"] = leg_tssvd(3, args.steps, args.warmup, A=A3,
+                                                ortho=T.ORTHO_ONCE)
+                del A3
+                torch.cuda.empty_cache()
+                _, A3 = generate(3, "f32")
+                legs["w3_f32_storage_fp64"] = leg_tssvd(3, args.steps, args.warmup, A=A3)
+                del A3
+                torch.cuda.empty_cache()
         except Exception as e:  # a failing secondary leg is reported, not fatal
             legs[leg] = dict(error=repr(e))
 
+    cbytes = spec["m"] * (64 * ((spec["n"] + 63) // 64)) * 2
+    a_streamed = (3 * mixed["abytes"] + (2 * spec["q"] - 1) * cbytes + cbytes
+                  if spec["q"] >= 1 else mixed["passes"] * mixed["abytes"])
     out = {
         "metric": METRIC,
         "value": round(mixed["value"], 2),
@@ -520,7 +577,13 @@ def main():
         "config": {"workload": "randomized rank-k SVD (Algorithm 7), 500000 x 8000 f32 (16 GB), "
                                "sigma_j = exp(-j/15) j<=600, + 1e-5 noise",
                    "m": spec["m"], "n": spec["n"], "k": spec["k"], "l": spec["l"], "q": spec["q"],
-                   "passes_over_A": mixed["passes"], "prec": "mixed"},
+                   "passes_over_A": mixed["passes"], "prec": "mixed",
+                   "passes_reading_bf16_copy": 2 * spec["q"] - 1,
+                   "bytes_of_A_streamed_per_call": a_streamed,
+                   "value_note": ("value counts bytes(A) as stored (f32) for every one of the "
+                                  "2q+2 passes; 2q-1 power-step passes stream the bfloat16 "
+                                  "copy (half those bytes) and the first pass also writes it: "
+                                  "bytes_of_A_streamed_per_call is what the passes move")},
         "roofline": roofline_of(mixed["kernels"]),
         "fp64_same_workload": {"value": round(fp64["value"], 2), "unit": "GB/s",
                                "ms_per_call": round(fp64["sec"] * 1e3, 4),

@@ -14,8 +14,9 @@ subspace, and the paper notes that the trailing SVD steps of Algorithm 1 are
 superfluous there; any orthonormal basis of the same column space leaves the
 final U, Sigma, V unchanged.  The oracle therefore takes Q from a Householder
 QR directly.  With wp > 0 (the paper's discard rule) the basis may lose
-columns, and ``mixes(r)`` supplies the r x r random orthogonal mixing applied
-before each factorization (Remark on randomness).
+columns.  No random mixing is applied before these factorizations: the printed
+Algorithm 7 errors are identical across independent runs, which a random
+mixing at a rank threshold would not give.
 
 For single-precision inputs every product is formed in double precision from
 the stored values (exact upcast), in row blocks to bound host memory.
@@ -49,7 +50,7 @@ def _at_times(A: np.ndarray, Q: np.ndarray) -> np.ndarray:
 
 
 def lowrank_ref(A: np.ndarray, Omega: np.ndarray, k: int, q: int, wp: float = 0.0,
-                mixes=None, return_basis: bool = False, tracking: str = "qr"):
+                return_basis: bool = False, tracking: str = "qr"):
     """Rank-k approximation U diag(sigma) V^T of A via Algorithm 7.
 
     tracking="lu" takes the intermediate bases of Algorithm 5 from an LU factorization
@@ -62,12 +63,11 @@ def lowrank_ref(A: np.ndarray, Omega: np.ndarray, k: int, q: int, wp: float = 0.
     l = Omega.shape[1]
     if not (0 < k <= l < min(m, n)):
         raise ValueError("need 0 < k <= l < min(m, n)")
-    if tracking not in ("qr", "lu") or (tracking == "lu" and (wp > 0.0 or mixes is not None)):
+    if tracking not in ("qr", "lu") or (tracking == "lu" and wp > 0.0):
         raise ValueError("tracking is 'qr', or 'lu' without the discard rule")
 
     def orth(Y):
-        mix = mixes(Y.shape[1]) if (mixes is not None and Y.shape[1] > 0) else None
-        return tsqr_ref(Y, wp, mix)[0]
+        return tsqr_ref(Y, wp)[0]
 
     track = orth if tracking == "qr" else lu_basis
     Qt = Omega                                          # step 1

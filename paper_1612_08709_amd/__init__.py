@@ -50,6 +50,24 @@ def _stream(device) -> C.c_void_p:
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def _check_omega(Omega, n: int, l: int, device):
+    """The sketch is read as a contiguous n x l float64 device array (or is None)."""
+    if Omega is None:
+        return
+    if Omega.dtype != torch.float64 or tuple(Omega.shape) != (n, l) or \
+            not Omega.is_contiguous() or Omega.device != torch.device(device):
+        raise ValueError("Omega must be a contiguous float64 n x l tensor on A's device")
+
+
+def _check_cotangent(t, shape, name, device):
+    """A cotangent, when given, must have the shape of the output it belongs to."""
+    if t is None:
+        return None
+    if tuple(t.shape) != tuple(shape) or t.device != torch.device(device):
+        raise ValueError(f"{name} must have shape {tuple(shape)} and live on A's device")
+    return t.to(torch.float64).contiguous()
+
+
 def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
@@ -143,10 +161,7 @@ class LowrankCall:
         self.info = _InfoBuf(dev)
 
     def run(self, Omega: torch.Tensor | None = None):
-        if Omega is not None:
-            if Omega.dtype != torch.float64 or tuple(Omega.shape) != (self.n, self.l) or \
-                    not Omega.is_contiguous() or Omega.device != self.A.device:
-                raise ValueError("Omega must be a contiguous float64 n x l tensor on A's device")
+        _check_omega(Omega, self.n, self.l, self.A.device)
         st = N.lib().lowrank_svd(_ptr(self.A), _dtype_code(self.A), self.m, self.n,
                                  self.A.stride(0), self.k, self.l, self.q, _ptr(Omega),
                                  _ptr(self.U), self.k, _ptr(self.S), _ptr(self.V), self.k,
@@ -169,6 +184,13 @@ def lowrank_svd_backward(A, k, l, q, Omega, U, S, V, gU=None, gS=None, gV=None,
     """dL/dA for cotangents (gU, gS, gV) of lowrank_svd's outputs; returns gA (A's dtype)."""
     _check_matrix(A)
     m, n = A.shape
+    k, l, q = int(k), int(l), int(q)
+    _check_omega(Omega, n, l, A.device)
+    # the cotangents are passed as contiguous float64 arrays, so their row strides are k;
+    # the library reads gU and gV with the ldu / ldv strides (U and V themselves are not read)
+    gU = _check_cotangent(gU, (m, k), "gU", A.device)
+    gS = _check_cotangent(gS, (k,), "gS", A.device)
+    gV = _check_cotangent(gV, (n, k), "gV", A.device)
     o = opts if opts is not None else make_opts(**kw)
     lib = N.lib()
     nb = C.c_size_t()
@@ -177,15 +199,10 @@ def lowrank_svd_backward(A, k, l, q, Omega, U, S, V, gU=None, gS=None, gV=None,
             "lowrank_svd_backward_workspace_bytes")
     work = _workspace(nb.value, A.device)
     gA = torch.empty_like(A)
-
-    def c64(t):
-        return None if t is None else t.to(torch.float64).contiguous()
-
-    gU, gS, gV = c64(gU), c64(gS), c64(gV)
     info = _InfoBuf(A.device)
     st = lib.lowrank_svd_backward(_ptr(A), _dtype_code(A), m, n, A.stride(0), k, l, q,
-                                  _ptr(Omega), _ptr(U), U.stride(0), _ptr(S), _ptr(V),
-                                  V.stride(0), _ptr(gU), _ptr(gS), _ptr(gV), _ptr(gA),
+                                  _ptr(Omega), _ptr(U), k, _ptr(S), _ptr(V), k,
+                                  _ptr(gU), _ptr(gS), _ptr(gV), _ptr(gA),
                                   gA.stride(0), info.ptr, _ptr(work), nb.value, C.byref(o),
                                   _stream(A.device))
     N.check(st, "lowrank_svd_backward")

@@ -40,7 +40,10 @@ __global__ void k_bw_core(const double* __restrict__ A1, const double* __restric
   const double g2ij = (j < k) ? G2[i * k + j] : 0.0;
   const double g2ji = (i < k) ? G2[j * k + i] : 0.0;
   double c = 0.0;
-  if (i != j) {
+  // Pairs with both indices past k multiply zero cotangents (G1 and G2 vanish there), and
+  // the trailing sketch values may repeat (exact zeros when rank(A) < l), so 1/(sj^2 - si^2)
+  // is not formed for them.
+  if (i != j && (i < k || j < k)) {
     const double f = 1.0 / ((sj - si) * (sj + si));
     c = f * (g2ij - g2ji) * sj + si * f * (A1[i * l + j] - A1[j * l + i]);
   } else if (i < k && Sbar) {

@@ -197,3 +197,25 @@ def test_python_structs_match_the_header():
     from paper_1612_08709_amd import _native as N
     assert [f for f, _ in N.Opts._fields_] == _header_struct_fields("tssvd_opts")
     assert [f for f, _ in N.Info._fields_] == _header_struct_fields("tssvd_info")
+
+
+def test_sketch_and_cotangent_checks_reject_misread_layouts(native):
+    """The binding passes Omega as a contiguous n x l float64 array and the cotangents with
+    their own row strides; anything else would be read out of bounds by the library, so it
+    is rejected (or copied) before the call."""
+    import torch
+    import paper_1612_08709_amd as T
+    n, l = 12, 5
+    ok = torch.zeros(n, l, dtype=torch.float64)
+    T._check_omega(ok, n, l, "cpu")
+    T._check_omega(None, n, l, "cpu")
+    for bad in (ok.float(), ok.T.contiguous().T, ok[:, :l - 1], torch.zeros(n + 1, l,
+                                                                              dtype=torch.float64)):
+        with pytest.raises(ValueError):
+            T._check_omega(bad, n, l, "cpu")
+    g = torch.zeros(7, 2 * 3, dtype=torch.float32)[:, ::2]          # 7 x 3, row stride 6
+    c = T._check_cotangent(g, (7, 3), "gU", "cpu")
+    assert c.dtype == torch.float64 and c.is_contiguous() and c.stride(0) == 3
+    assert T._check_cotangent(None, (7, 3), "gU", "cpu") is None
+    with pytest.raises(ValueError):
+        T._check_cotangent(torch.zeros(7, 4), (7, 3), "gU", "cpu")

@@ -68,7 +68,8 @@ def test_backward_partial_cotangents():
 
 
 def test_backward_vs_central_differences_of_gpu_forward():
-    """FD instance of the differentiation workload: 2,000 x 50, sigma_j = 1/j, k=16, l=24, q=2."""
+    """FD instance of the differentiation workload: 2,000 x 50, sigma_j = 1/j, k=16, l=24, q=2;
+    32 seeded unit directions, each with the best of three step sizes."""
     m, n, k, l, q = 2000, 50, 16, 24, 2
     A, Om, w, GU, GV = _instance(m, n, k, l, q, 5)
     g = _gpu_grad(A, Om, k, l, q, w, GU, GV)
@@ -81,7 +82,7 @@ def test_backward_vs_central_differences_of_gpu_forward():
 
     rng = sm.rng_for(5, "fd")
     worst = 0.0
-    for _ in range(8):
+    for _ in range(32):
         E = rng.standard_normal(A.shape)
         E /= np.linalg.norm(E)
         exact = float(np.sum(g * E))
@@ -166,3 +167,55 @@ def test_autograd_function():
     torch.cuda.synchronize()
     gr, _ = grad_ref.grad_ref(A, Om, k, q, w, GU, GV)
     assert _rel(host(At.grad), gr) <= 1e-9
+
+
+def test_backward_trailing_plateau_is_finite():
+    """A spectrum that is flat past k: the sketch lies in range(A), so the trailing singular
+    values of B = Q^T A repeat (equal up to rounding).  The pairs with both indices past k
+    carry zero cotangents and must not turn 1/(s_j^2 - s_i^2) into NaN."""
+    m, n, k, l, q = 1200, 150, 6, 14, 1
+    sigma = np.concatenate([1.0 / np.arange(1, k + 1), np.full(n - k, 0.05)])
+    A = sm.planted(m, n, sigma, workload=93)
+    Om = sm.sketch(n, l, 93)
+    w = sm.gaussian(k, 93, "w")
+    GU = sm.gaussian((m, k), 93, "GU")
+    GV = sm.gaussian((n, k), 93, "GV")
+    g = _gpu_grad(A, Om, k, l, q, w, GU, GV)
+    assert np.all(np.isfinite(g))
+    gr, _ = grad_ref.grad_ref(A, Om, k, q, w, GU, GV)
+    if np.all(np.isfinite(gr)):
+        assert _rel(g, gr) <= 1e-8
+
+
+def test_backward_strided_outputs_and_cotangents():
+    """U and V sliced from wider tensors and non-contiguous cotangents: the binding passes
+    the cotangents' own row strides, so the result equals the contiguous call's."""
+    m, n, k, l, q = 900, 120, 5, 10, 1
+    A, Om, w, GU, GV = _instance(m, n, k, l, q, 94)
+    Ad, Omd = dev(A), dev(Om)
+    U, S, V, _ = T.lowrank_svd(Ad, k, l, q, Omd)
+    Uw = torch.zeros(m, k + 7, dtype=torch.float64, device=Ad.device)
+    Vw = torch.zeros(n, k + 3, dtype=torch.float64, device=Ad.device)
+    Uw[:, :k] = U
+    Vw[:, :k] = V
+    gUw = torch.zeros(m, 2 * k, dtype=torch.float64, device=Ad.device)
+    gUw[:, ::2] = dev(GU)
+    gVt = dev(np.ascontiguousarray(GV.T)).T          # n x k, column-major view
+    g1 = T.lowrank_svd_backward(Ad, k, l, q, Omd, Uw[:, :k], S, Vw[:, :k], gUw[:, ::2], dev(w),
+                                gVt)
+    g2 = T.lowrank_svd_backward(Ad, k, l, q, Omd, U, S, V, dev(GU), dev(w), dev(GV))
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+
+
+def test_backward_rejects_bad_sketch_and_cotangents():
+    m, n, k, l, q = 300, 60, 4, 8, 1
+    A, Om, w, GU, GV = _instance(m, n, k, l, q, 95)
+    Ad = dev(A)
+    U, S, V, _ = T.lowrank_svd(Ad, k, l, q, dev(Om))
+    for bad in (dev(Om).float(), dev(Om).T.contiguous().T, dev(Om)[:, :l - 1], dev(Om).cpu()):
+        with pytest.raises(ValueError):
+            T.lowrank_svd_backward(Ad, k, l, q, bad, U, S, V, dev(GU), dev(w), dev(GV))
+    with pytest.raises(ValueError):
+        T.lowrank_svd_backward(Ad, k, l, q, dev(Om), U, S, V, dev(GU)[:, :k - 1], dev(w),
+                               dev(GV))
