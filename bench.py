@@ -463,6 +463,89 @@ def leg_backward(steps, warmup):
     return out
 
 
+PROBE_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_build",
+                         "libtssvd_probe.so")
+
+
+def run_probe():
+    """Ceilings measured on this GPU (bench_probe.hip): FP64/FP32 MFMA and FP64 FMA rates
+    at 1-4 waves per SIMD, MFMA and FMA waves together, and HBM rates of a streaming read, a
+    read with a half-size write (the first mixed power pass) and a copy.  One JSON line."""
+    import ctypes as C
+    import torch
+    if not os.path.exists(PROBE_LIB):
+        raise RuntimeError(f"{PROBE_LIB} is missing: run __graft_entry__.build() first")
+    lib = C.CDLL(PROBE_LIB)
+    lib.probe_compute.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p,
+                                  C.POINTER(C.c_double), C.c_void_p]
+    lib.probe_stream.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_void_p,
+                                 C.c_void_p]
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream()
+    sp = C.c_void_p(stream.cuda_stream)
+    out = torch.zeros(1 << 16, dtype=torch.float64, device=dev)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b) / 1e3)
+        return float(np.median(ts))
+
+    res = {"cus": cus, "compute": [], "stream": []}
+    names = {0: "mfma_f64_16x16x4", 1: "mfma_f32_16x16x4", 2: "fma_f64_vector",
+             3: "mfma_f64_16x16x4 + fma_f64 (half the waves each)"}
+    for kind in (0, 1, 2, 3):
+        for wps in (1, 2, 4):  # waves per SIMD: 4 waves per workgroup, wps workgroups per CU
+            blocks = cus * wps
+            iters = 2000 if kind != 2 else 8000
+            fl = C.c_double()
+
+            def go():
+                st = lib.probe_compute(kind, blocks, iters, C.c_void_p(out.data_ptr()),
+                                       C.byref(fl), sp)
+                assert st == 0
+            t = timed(go)
+            res["compute"].append({"probe": names[kind], "waves_per_simd": wps,
+                                   "tflops": round(fl.value / t / 1e12, 2),
+                                   "ms": round(t * 1e3, 3)})
+            log("probe", res["compute"][-1])
+    nbytes = 16 * (1 << 30)
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    n16 = nbytes // 16
+    for kind, name, wbytes in ((0, "read 16 GiB", 0), (1, "read 16 GiB + write 8 GiB", nbytes // 2),
+                               (2, "copy 8 GiB", None)):
+        if kind == 2:
+            n = n16 // 2
+            dst = torch.empty(nbytes // 8, dtype=torch.float32, device=dev)
+            rbytes, wb = nbytes // 2, nbytes // 2
+        else:
+            n = n16
+            dst = (torch.empty(nbytes // 8, dtype=torch.float32, device=dev) if kind == 1
+                   else torch.empty(1 << 16, dtype=torch.float32, device=dev))
+            rbytes, wb = nbytes, wbytes
+        for wpc in (2, 4, 8):
+            blocks = cus * wpc
+
+            def go():
+                assert lib.probe_stream(kind, blocks, C.c_void_p(src.data_ptr()), n,
+                                        C.c_void_p(dst.data_ptr()), sp) == 0
+            t = timed(go)
+            res["stream"].append({"probe": name, "workgroups_per_cu": wpc,
+                                  "gbs": round((rbytes + wb) / t / 1e9, 1),
+                                  "ms": round(t * 1e3, 3)})
+            log("probe", res["stream"][-1])
+        del dst
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -486,7 +569,12 @@ def main():
                          "kernels by grid size")
     ap.add_argument("--command", default="",
                     help="the profiling command, recorded in a summary")
+    ap.add_argument("--probe", action="store_true",
+                    help="measure the MFMA, FMA and HBM ceilings (bench_probe.hip) and exit")
     args = ap.parse_args()
+    if args.probe:
+        run_probe()
+        return
     if args.summarize_pmc:
         print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.command))
         return

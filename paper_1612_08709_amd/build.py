@@ -57,6 +57,15 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, OUT)
+    # throughput probes for bench.py --probe (not part of the library)
+    probe_src = os.path.join(ROOT, "bench_probe.hip")
+    if os.path.exists(probe_src):
+        probe_out = os.path.join(BUILD, "libtssvd_probe.so")
+        r = subprocess.run([hipcc, *FLAGS, "-shared", "-o", probe_out + ".tmp", probe_src],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {probe_src}:\n{r.stderr}")
+        os.replace(probe_out + ".tmp", probe_out)
     if verbose:
         print(f"built {OUT} ({len(srcs)} sources, {ARCH})")
     return OUT
