@@ -175,6 +175,28 @@ int tssvd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
           void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * tssvd_noalloc — tssvd without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, options, results and errors as tssvd; the scratch memory is
+ * a fixed array of TSSVD_NOALLOC_SCRATCH_BYTES inside the library's code object, one per
+ * GPU, held from its first use until the process ends.  The call allocates nothing and
+ * does not record measurement events.
+ *   - Sizes whose tssvd_workspace_bytes exceeds TSSVD_NOALLOC_SCRATCH_BYTES return
+ *     TSSVD_E_UNSUPPORTED (nothing is enqueued).  In this version n = 100 fits
+ *     m <= 14,720 rows, n = 64 fits m <= 44,800 and n = 20 fits m <= 303,040.
+ *   - The array belongs to the current device (hipGetDevice) of the calling thread;
+ *     `stream` must be a stream of that device.  Its address is looked up on the first
+ *     call on each device.
+ *   - Every call on one GPU shares that GPU's array and leaves its contents behind: calls
+ *     that may overlap on one GPU (different streams, or different host threads without
+ *     ordering) race and must be serialized by the caller.
+ * ------------------------------------------------------------------------------------- */
+#define TSSVD_NOALLOC_SCRATCH_BYTES (64u << 20)
+int tssvd_noalloc(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
+                  double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+                  tssvd_info* info, const tssvd_opts* opts, void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * lowrank_svd — rank-k approximation A ~ U diag(S) V^T by Algorithm 7 with sketch width
  * l and q power iterations (the paper's i): 2q+2 passes over A.
  *   A     : m x n, a_dtype, stride lda.  Requires 0 < k <= l < min(m, n), l <= TSSVD_N_MAX,

@@ -21,7 +21,7 @@ from ._native import (F32, F64, ORTHO_AUTO, ORTHO_ONCE, ORTHO_TWICE, PREC_FP64, 
                       PREC_MIXED, TSSVD_N_MAX, TSSVD_TSQR_N_MAX, FLAG_F32_MFMA_FINAL,
                       FLAG_NO_A_COPY, FLAG_GRAM, FLAG_LU, FLAG_MIX)
 
-__all__ = ["tsqr", "tssvd", "lowrank_svd", "lowrank_svd_backward", "LowRankSVD", "make_opts",
+__all__ = ["tsqr", "tssvd", "tssvd_noalloc", "lowrank_svd", "lowrank_svd_backward", "LowRankSVD", "make_opts",
            "PREC_FP64", "PREC_MIXED", "ORTHO_AUTO", "ORTHO_ONCE", "ORTHO_TWICE",
            "FLAG_F32_MFMA_FINAL", "FLAG_NO_A_COPY", "FLAG_GRAM",
            "FLAG_LU", "FLAG_MIX"]
@@ -135,6 +135,24 @@ def tssvd(A: torch.Tensor, opts: N.Opts | None = None, **kw):
     st = lib.tssvd(_ptr(A), _dtype_code(A), m, n, A.stride(0), _ptr(U), n, _ptr(S), _ptr(V), n,
                    info.ptr, _ptr(work), nb.value, C.byref(o), _stream(A.device))
     N.check(st, "tssvd")
+    return U, S, V, info.read()
+
+
+def tssvd_noalloc(A: torch.Tensor, opts: N.Opts | None = None, **kw):
+    """tssvd through the entry point that takes no workspace (the library's fixed per-GPU
+    scratch array).  Returns (U, S, V, info) like tssvd."""
+    _check_matrix(A)
+    m, n = A.shape
+    o = opts if opts is not None else make_opts(**kw)
+    U = torch.empty(m, n, dtype=torch.float64, device=A.device)
+    S = torch.empty(n, dtype=torch.float64, device=A.device)
+    V = torch.empty(n, n, dtype=torch.float64, device=A.device)
+    info = _InfoBuf(A.device)
+    with torch.cuda.device(A.device):
+        st = N.lib().tssvd_noalloc(_ptr(A), _dtype_code(A), m, n, A.stride(0), _ptr(U), n,
+                                   _ptr(S), _ptr(V), n, info.ptr, C.byref(o),
+                                   _stream(A.device))
+    N.check(st, "tssvd_noalloc")
     return U, S, V, info.read()
 
 

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libtssvd.so")
 
 TSSVD_N_MAX = 100
 TSSVD_TSQR_N_MAX = 128
+TSSVD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 OK, E_INVALID_ARG, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, 1, 2, 3, 4
 F64, F32 = 0, 1
@@ -29,7 +30,7 @@ FLAG_MIX = 16
 EXPORTS = (
     "tssvd_default_opts", "tssvd_status_string", "tssvd_version",
     "tsqr_workspace_bytes", "tsqr",
-    "tssvd_workspace_bytes", "tssvd",
+    "tssvd_workspace_bytes", "tssvd", "tssvd_noalloc",
     "lowrank_svd_workspace_bytes", "lowrank_svd",
     "lowrank_svd_backward_workspace_bytes", "lowrank_svd_backward",
     "tssvd_profile_enable", "tssvd_profile_read",
@@ -70,6 +71,7 @@ def _declare(lib):
     lib.tsqr.argtypes = [P, I32, I64, I64, I64, P, I64, P, I64, P, SZ, P]
     lib.tssvd_workspace_bytes.argtypes = [I64, I64, I32, C.POINTER(Opts), C.POINTER(SZ)]
     lib.tssvd.argtypes = [P, I32, I64, I64, I64, P, I64, P, P, I64, P, P, SZ, C.POINTER(Opts), P]
+    lib.tssvd_noalloc.argtypes = [P, I32, I64, I64, I64, P, I64, P, P, I64, P, C.POINTER(Opts), P]
     lib.lowrank_svd_workspace_bytes.argtypes = [I64, I64, I64, I64, I64, I32, C.POINTER(Opts),
                                                 C.POINTER(SZ)]
     lib.lowrank_svd.argtypes = [P, I32, I64, I64, I64, I64, I64, I64, P, P, I64, P, P, I64, P,
@@ -82,7 +84,7 @@ def _declare(lib):
     lib.tssvd_profile_enable.restype = C.c_int
     lib.tssvd_profile_read.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.tssvd_profile_read.restype = C.c_int
-    for name in ("tsqr_workspace_bytes", "tsqr", "tssvd_workspace_bytes", "tssvd",
+    for name in ("tsqr_workspace_bytes", "tsqr", "tssvd_workspace_bytes", "tssvd", "tssvd_noalloc",
                  "lowrank_svd_workspace_bytes", "lowrank_svd",
                  "lowrank_svd_backward_workspace_bytes", "lowrank_svd_backward"):
         getattr(lib, name).restype = C.c_int

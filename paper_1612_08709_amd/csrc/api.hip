@@ -8,6 +8,7 @@
 #include "internal.h"
 
 #include <climits>
+#include <mutex>
 
 using namespace tsv;
 
@@ -605,9 +606,21 @@ int tssvd_workspace_bytes(int64_t m, int64_t n, int32_t a_dtype, const tssvd_opt
   return TSSVD_OK;
 }
 
-int tssvd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double* U,
-          int64_t ldu, double* S, double* V, int64_t ldv, tssvd_info* info, void* work,
-          size_t work_bytes, const tssvd_opts* opts, void* stream) {
+}  // extern "C"
+
+// Scratch of tssvd_noalloc: device memory in the code object, one copy per GPU, held
+// until the process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host the name is only a stand-in); it passes the device address that
+// hipGetSymbolAddress returns for the current device, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[TSSVD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// The body of tssvd; prof = false keeps the measurement markers (which create HIP events
+// on first use) out of the call.
+int tssvd_run(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double* U,
+              int64_t ldu, double* S, double* V, int64_t ldv, tssvd_info* info, void* work,
+              size_t work_bytes, const tssvd_opts* opts, void* stream, bool prof) {
   if (!A || !U || !S || !V || bad_dtype(a_dtype) || n < 1 || m < n || lda < n || ldu < n ||
       ldv < n)
     return TSSVD_E_INVALID_ARG;
@@ -628,7 +641,7 @@ int tssvd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, dou
   // The one-sided Jacobi runs on R^T (R^T W = P S gives R = W S P^T: U~ = W, V~ = P),
   // whose columns converge in about half the sweeps that R's need when R's columns are
   // mixed (measured 10 vs 23 sweeps for n = 100, sigma from 1 to 1e-6).
-  TRY(tsqr_factor(w.p, A, a_dtype, lda, s, true));
+  TRY(tsqr_factor(w.p, A, a_dtype, lda, s, prof));
   const unsigned nb = (unsigned)((ni * ni + 255) / 256);
   if (!mix) {
     TRY(jacobi_svd(tsqr_root(w.p), ni, ni, 1, o.working_precision, o.max_jacobi_sweeps, 1,
@@ -652,7 +665,7 @@ int tssvd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, dou
     TRY(tsqr_apply(w.pn, w.Mu, ni, w.Ut, n, s));                       // Q1 U~
     TRY(sign_fix_cols(w.Vt, n, ni, ni, w.Ut, ni, ni, s));
   }
-  TRY(tsqr_apply(w.p, w.Ut, ni, U, ldu, s, true));
+  TRY(tsqr_apply(w.p, w.Ut, ni, U, ldu, s, prof));
   TRY(copy_matrix(w.S, 1, ni, ni, S, ni, s));
   TRY(copy_matrix(w.Vt, n, ni, n, V, ldv, s));
   if (o.ortho == TSSVD_ORTHO_ONCE) return TSSVD_OK;
@@ -680,6 +693,51 @@ int tssvd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, dou
   TRY(copy_matrix(w.S2, 1, ni, ni, S, ni, s, w.gate));
   TRY(copy_matrix(w.V2, n, ni, n, V, ldv, s, w.gate));
   return hip_status(hipGetLastError());
+}
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+int scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return TSSVD_E_HIP;
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return TSSVD_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TSSVD_E_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TSSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tssvd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, double* U,
+          int64_t ldu, double* S, double* V, int64_t ldv, tssvd_info* info, void* work,
+          size_t work_bytes, const tssvd_opts* opts, void* stream) {
+  return tssvd_run(A, a_dtype, m, n, lda, U, ldu, S, V, ldv, info, work, work_bytes, opts,
+                   stream, true);
+}
+
+int tssvd_noalloc(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
+                  double* U, int64_t ldu, double* S, double* V, int64_t ldv, tssvd_info* info,
+                  const tssvd_opts* opts, void* stream) {
+  if (!A || !U || !S || !V || bad_dtype(a_dtype) || n < 1 || m < n || lda < n || ldu < n ||
+      ldv < n)
+    return TSSVD_E_INVALID_ARG;
+  if (n > TSSVD_N_MAX) return TSSVD_E_UNSUPPORTED;
+  if (tssvd_layout(m, (int)n, nullptr).bytes > (size_t)TSSVD_NOALLOC_SCRATCH_BYTES)
+    return TSSVD_E_UNSUPPORTED;
+  void* work = nullptr;
+  const int st = scratch_address(&work);
+  if (st != TSSVD_OK) return st;
+  return tssvd_run(A, a_dtype, m, n, lda, U, ldu, S, V, ldv, info, work,
+                   (size_t)TSSVD_NOALLOC_SCRATCH_BYTES, opts, stream, false);
 }
 
 }  // extern "C"

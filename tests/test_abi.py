@@ -219,3 +219,24 @@ def test_sketch_and_cotangent_checks_reject_misread_layouts(native):
     assert T._check_cotangent(None, (7, 3), "gU", "cpu") is None
     with pytest.raises(ValueError):
         T._check_cotangent(torch.zeros(7, 4), (7, 3), "gU", "cpu")
+
+
+def test_noalloc_rejects_before_touching_the_device(native):
+    """tssvd_noalloc checks its arguments and the scratch limit on the host first."""
+    lib, N = native.lib(), native
+    o = N.default_opts()
+    fake = C.c_void_p(0x1000)
+    # workspace need beyond the fixed scratch array: rejected, nothing enqueued
+    st = lib.tssvd_noalloc(fake, N.F64, 200000, 100, 100, fake, 100, fake, fake, 100, None,
+                           C.byref(o), None)
+    assert st == N.E_UNSUPPORTED
+    nb = C.c_size_t()
+    assert lib.tssvd_workspace_bytes(200000, 100, N.F64, C.byref(o), C.byref(nb)) == N.OK
+    assert nb.value > N.TSSVD_NOALLOC_SCRATCH_BYTES
+    assert lib.tssvd_noalloc(None, N.F64, 1000, 10, 10, fake, 10, fake, fake, 10, None,
+                             C.byref(o), None) == N.E_INVALID_ARG
+    assert lib.tssvd_noalloc(fake, N.F64, 1000, 101, 101, fake, 101, fake, fake, 101, None,
+                             C.byref(o), None) == N.E_UNSUPPORTED
+    text = open(HEADER).read()
+    assert "#define TSSVD_NOALLOC_SCRATCH_BYTES (64u << 20)" in text
+    assert N.TSSVD_NOALLOC_SCRATCH_BYTES == 64 << 20
