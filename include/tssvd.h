@@ -183,7 +183,7 @@ int tssvd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
  * does not record measurement events.
  *   - Sizes whose tssvd_workspace_bytes exceeds TSSVD_NOALLOC_SCRATCH_BYTES return
  *     TSSVD_E_UNSUPPORTED (nothing is enqueued).  In this version n = 100 fits
- *     m <= 14,720 rows, n = 64 fits m <= 44,800 and n = 20 fits m <= 303,040.
+ *     m <= 13,056 rows, n = 64 fits m <= 31,872 and n = 20 fits m <= 303,040.
  *   - The array belongs to the current device (hipGetDevice) of the calling thread;
  *     `stream` must be a stream of that device.  Its address is looked up on the first
  *     call on each device.

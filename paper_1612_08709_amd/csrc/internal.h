@@ -45,6 +45,13 @@ struct TsqrPlan {
   std::vector<double*> Slev;  // seeds per level: cnt[L] * n * n
   // When non-NULL, every kernel of the plan returns at once if *gate == 0 (device flag).
   const int* gate = nullptr;
+  // Blocked leaf (33 <= n <= 128): ntw = 16-column tiles, 256-row blocks; per block the
+  // reflector tails V (256 x 16 ntw), the panel factors T_p and the products Z_cp = V_c^T V_p.
+  // Vleaf then points at Vwy (callers use it as m x n scratch) and tauleaf is unused.
+  int ntw = 0;
+  double* Vwy = nullptr;
+  double* Twy = nullptr;
+  double* Zwy = nullptr;
 };
 
 // nr (8 or 16, narrow tiles only) and wtarget (leaf workgroups) override the defaults.
@@ -58,6 +65,12 @@ double* tsqr_root(const TsqrPlan& p);
 // out (m x k, stride ldo).  S is copied first, so it may live anywhere.
 hipError_t tsqr_apply(const TsqrPlan& p, const double* S, int k, double* out, int64_t ldo,
                       hipStream_t s, bool prof = false);
+
+// Blocked leaf kernels (csrc/tsqr_wy.hip), used by tsqr_factor / tsqr_apply when ntw > 0.
+hipError_t wy_factor(const TsqrPlan& p, const void* A, int a_dtype, int64_t lda, hipStream_t s);
+hipError_t wy_apply(const TsqrPlan& p, int k, double* out, int64_t ldo, hipStream_t s);
+// doubles of storage per 256-row block: V, the ntw panel factors T_p and the Z_cp pairs
+size_t wy_block_doubles(int ntw);
 
 // ------------------------------------------------------------------ small SVD (Jacobi)
 // SVD of M (n x n row-major, stride ldm; its transpose when transpose != 0):

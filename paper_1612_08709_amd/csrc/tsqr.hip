@@ -362,11 +362,18 @@ TsqrPlan tsqr_plan(int64_t m, int n, int nr, int wtarget) {
   if ((nr == 8 || nr == 16) && p.nc <= 4) p.nr = nr;
   p.B = 16 * p.nr;
   p.BT = 16 * p.tnr;
+  // n >= 33: blocked leaf on the matrix cores, 128-row blocks, 256-thread workgroups, two
+  // per CU (one for n > 112, whose carried factor needs more of the local data share).
+  if (n >= 33 && n <= 128) {
+    p.ntw = (n + 15) / 16;
+    p.B = 128;
+  }
   p.nblocks = (m + p.B - 1) / p.B;
   // About as many leaf workgroups as can be resident at once (two per CU for the wide
-  // tiles, four for the narrow ones): fewer would idle CUs, more would only deepen the
-  // merge tree.
-  const int64_t target = wtarget > 0 ? wtarget : (p.nc >= 4) ? 512 : 1024;
+  // tiles, four for the narrow ones, one for the blocked leaf): fewer would idle CUs, more
+  // would only deepen the merge tree.
+  const int64_t target = wtarget > 0 ? wtarget : p.ntw ? (p.ntw <= 7 ? 512 : 256)
+                                                        : (p.nc >= 4) ? 512 : 1024;
   int64_t W = p.nblocks < target ? p.nblocks : target;
   p.bpw = (int)((p.nblocks + W - 1) / W);
   p.W = (int)((p.nblocks + p.bpw - 1) / p.bpw);
@@ -380,8 +387,17 @@ TsqrPlan tsqr_plan(int64_t m, int n, int nr, int wtarget) {
 
 void tsqr_carve(TsqrPlan& p, Carver& c) {
   const int n = p.n;
-  p.Vleaf = c.take<double>((size_t)p.nblocks * n * p.B);
-  p.tauleaf = c.take<double>((size_t)p.nblocks * n);
+  if (p.ntw) {
+    const int nt = p.ntw;
+    p.Vwy = c.take<double>((size_t)p.nblocks * p.B * 16 * nt);
+    p.Twy = c.take<double>((size_t)p.nblocks * nt * 256);
+    p.Zwy = c.take<double>((size_t)p.nblocks * (nt > 1 ? nt * (nt - 1) / 2 : 1) * 256);
+    p.Vleaf = p.Vwy;
+    p.tauleaf = nullptr;
+  } else {
+    p.Vleaf = c.take<double>((size_t)p.nblocks * n * p.B);
+    p.tauleaf = c.take<double>((size_t)p.nblocks * n);
+  }
   const int L = (int)p.cnt.size();
   p.Rlev.assign(L, nullptr);
   p.Slev.assign(L, nullptr);
@@ -405,7 +421,10 @@ static hipError_t factor_impl(const TsqrPlan& p, const void* A, int a_dtype, int
   const int n = p.n;
   const size_t lds = (size_t)(tri_size(n) + 2 * 16 * NR + n) * sizeof(double);
   if (prof) prof_begin(TSSVD_PROF_LEAF_FACTOR, s);
-  if (a_dtype == TSSVD_F64)
+  if (p.ntw) {
+    hipError_t e = wy_factor(p, A, a_dtype, lda, s);
+    if (e != hipSuccess) return e;
+  } else if (a_dtype == TSSVD_F64)
     hipLaunchKernelGGL((k_leaf_factor<NC, NR, double>), dim3(p.W), dim3(256), lds, s,
                        (const double*)A, lda, p.m, n, p.bpw, p.nblocks, p.Vleaf, p.tauleaf,
                        p.Rlev[0], p.gate);
@@ -436,8 +455,13 @@ static hipError_t apply_impl(const TsqrPlan& p, const double* S, int k, double* 
                        p.Slev[l + 1], p.cnt[l], n, k, p.G, p.Vtree[l], p.tautree[l],
                        p.Slev[l], p.gate);
   if (prof) prof_begin(TSSVD_PROF_LEAF_APPLY, s);
-  hipLaunchKernelGGL((k_leaf_apply<NC, NR>), dim3(p.W), dim3(256), lds, s, p.Vleaf,
-                     p.tauleaf, p.Slev[0], n, k, p.bpw, p.nblocks, p.m, out, ldo, p.gate);
+  if (p.ntw) {
+    e = wy_apply(p, k, out, ldo, s);
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL((k_leaf_apply<NC, NR>), dim3(p.W), dim3(256), lds, s, p.Vleaf,
+                       p.tauleaf, p.Slev[0], n, k, p.bpw, p.nblocks, p.m, out, ldo, p.gate);
+  }
   if (prof) prof_end(TSSVD_PROF_LEAF_APPLY, s);
   return hipGetLastError();
 }

@@ -127,9 +127,14 @@ def test_deterministic_bitwise():
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("m,n", [(128, 128), (5000, 7), (70001, 100)])
+@pytest.mark.parametrize("m,n", [(128, 128), (5000, 7), (70001, 100), (33, 33), (255, 40),
+                                 (256, 48), (257, 64), (3001, 97), (20000, 113),
+                                 (600001, 100), (70001, 128)])
 def test_tsqr_factor_vs_householder(m, n):
-    """R equals LAPACK's Householder R up to row signs; Q R = A; Q^T Q = I."""
+    """R equals LAPACK's Householder R up to row signs; Q R = A; Q^T Q = I.  The shapes
+    with n >= 33 run the blocked leaf (256-row blocks, 16-column panels): one partial block,
+    exactly one block and one row past it, a last panel holding one real column (n = 97,
+    113), and chains of several blocks per workgroup (m = 70,001 and 600,001)."""
     flush_print("case tsqr", m, n)
     A = _graded(m, n, seed=m + n)
     Q, R = T.tsqr(dev(A))
@@ -143,12 +148,14 @@ def test_tsqr_factor_vs_householder(m, n):
     assert checks.ortho_spec(Q) < 1e-13
 
 
-def test_tsqr_float32_input():
-    A32 = _graded(9000, 20, seed=3).astype(np.float32)
+@pytest.mark.parametrize("m,n", [(9000, 20), (70001, 100)])
+def test_tsqr_float32_input(m, n):
+    A32 = _graded(m, n, seed=3).astype(np.float32)
     Q, R = T.tsqr(dev(A32))
     torch.cuda.synchronize()
     Q, R = host(Q), host(R)
     np.testing.assert_allclose(Q @ R, A32.astype(np.float64), atol=1e-12)
+    assert checks.ortho_spec(Q) < 1e-13
 
 
 def _workload3(dtype):
