@@ -25,7 +25,9 @@
  *   - Singular values are descending and non-negative.  Sign convention: each pair
  *     (u_j, v_j) is oriented so that w^T v_j >= 0 with w_i = frac((i+1) g) - 1/2,
  *     g = (sqrt(5)-1)/2, i = 0..n-1.  Triplets past the numerical rank (discard rule,
- *     working_precision > 0) have sigma = 0 and zero columns in U and V.
+ *     working_precision > 0) have sigma = 0 and zero columns in U and V.  With
+ *     working_precision = 0 a singular value that comes out exactly 0 (an exactly
+ *     rank-deficient A) has a zero column in U: A does not determine that direction.
  *   - Results are bitwise reproducible for identical inputs, options and sizes (fixed
  *     reduction orders, no floating-point atomics).
  *   - Calls that share a `work` buffer must be ordered on one stream.
@@ -58,18 +60,31 @@ typedef enum { TSSVD_F64 = 0, TSSVD_F32 = 1 } tssvd_dtype;
 
 typedef enum {
   TSSVD_PREC_FP64 = 0,       /* every product and factorization in float64              */
-  TSSVD_PREC_MIXED = 1       /* lowrank_svd: power-iteration products in bfloat16 with
-                                float32 accumulation; final sketch and B products with
-                                float32-exact inputs (three bfloat16 pieces per value) and
-                                float32 accumulation; TSQR, small SVD and the second
-                                orthonormalization in float64.  Requires a_dtype ==
-                                TSSVD_F32.  tssvd: A is read as stored, all arithmetic
-                                float64.                                                */
+  TSSVD_PREC_MIXED = 1       /* Requires a_dtype == TSSVD_F32 (else
+                                TSSVD_E_INVALID_ARG).  lowrank_svd: power-iteration
+                                products in bfloat16 with float32 accumulation; final
+                                sketch and B products with float32-exact inputs (three
+                                bfloat16 pieces per value) and float32 accumulation;
+                                TSQR, small SVD and the second orthonormalization in
+                                float64.  tssvd (33 <= n; no discard rule, mixing or
+                                Gram route, else TSSVD_E_UNSUPPORTED): Algorithm 2 with
+                                its first orthonormalization in float32 (TSQR leaf
+                                reflectors, their matrix-core products and U1 = Q1 U1~;
+                                merge tree and small SVD in float64) and its second in
+                                float64 (Cholesky QR of the float32 U1: U = U1 R2^-1 P);
+                                AUTO runs the second pass always, ONCE returns U1.
+                                For exactly rank-deficient A the first pass can lose
+                                a direction (a column of U1 with norm under 0.03 after
+                                the earlier ones are taken out): the second pass drops
+                                it as an exact zero singular value (sigma = 0, zero
+                                column of U).                                          */
 } tssvd_prec;
 
 typedef enum {
-  TSSVD_ORTHO_AUTO = 0,      /* measure ||U^T U - I||_F and run the second
-                                orthonormalization only if it exceeds reorth_tol       */
+  TSSVD_ORTHO_AUTO = 0,      /* run the second orthonormalization only if
+                                ||U^T U - I||_2 > reorth_tol (decided exactly from the
+                                Gram matrix G: (1 + tol) I - G and G - (1 - tol) I both
+                                pass a Cholesky factorization, or ||G - I||_F <= tol)  */
   TSSVD_ORTHO_ONCE = 1,      /* Algorithm 1: one orthonormalization                     */
   TSSVD_ORTHO_TWICE = 2      /* Algorithm 2: always orthonormalize twice                */
 } tssvd_ortho;
@@ -135,7 +150,8 @@ typedef struct {
   int32_t sweeps;            /* Jacobi sweeps used by the last small SVD                  */
   int32_t reorth;            /* 1 if a second orthonormalization pass ran                 */
   double ortho;              /* ||Q^T Q - I||_F of the orthonormal factor before the
-                                conditional second pass; -1 when not measured            */
+                                conditional second pass (an upper bound of the spectral
+                                norm the AUTO gate tests); -1 when not measured          */
 } tssvd_info;
 
 void tssvd_default_opts(tssvd_opts* opts);

@@ -43,12 +43,44 @@ int hip_status(hipError_t e) { return e == hipSuccess ? TSSVD_OK : TSSVD_E_HIP; 
   } while (0)
 
 // ---------------------------------------------------------------- orthonormality gate
-// ortho = ||Q^T Q - I||_F (an upper bound of the spectral norm); gate = 1 when the
-// second orthonormalization must run (always for TWICE, ortho > tol for AUTO).
-__global__ void k_ortho_gate(const double* __restrict__ G, int k, int mode, double tol,
-                             double* __restrict__ ortho_out, int* __restrict__ gate,
-                             tssvd_info* info) {
+// M = sgn (G - shift I) (k x k, packed upper triangle in LDS) positive definite?  Right-
+// looking Cholesky, one barrier per step; false at the first pivot that is not positive and
+// finite (the pivot is read by every thread, so all leave together).
+__device__ bool gate_chol_pd(double* M, const double* __restrict__ G, int k, double sgn,
+                             double shift) {
+  const int tid = threadIdx.x;
+  auto off = [k](int i) { return i * k - (i * (i - 1)) / 2; };
+  for (int idx = tid; idx < k * k; idx += 256) {
+    const int i = idx / k, j = idx - i * k;
+    if (j >= i) M[off(i) + (j - i)] = sgn * (G[idx] - (i == j ? shift : 0.0));
+  }
+  __syncthreads();
+  const int ti = tid >> 4, tj = tid & 15;
+  for (int kk = 0; kk < k; ++kk) {
+    const double piv = M[off(kk)];
+    if (!(piv > 0.0) || !isfinite(piv)) return false;
+    const double inv = 1.0 / piv;
+    const double* Mk = M + off(kk) - kk;  // Mk[j] = M(kk, j)
+    for (int i = kk + 1 + ti; i < k; i += 16) {
+      const double f = Mk[i] * inv;
+      double* Mi = M + off(i) - i;
+      for (int j = i + tj; j < k; j += 16) Mi[j] = fma(-f, Mk[j], Mi[j]);
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// G = Q^T Q (k x k, k <= TSSVD_N_MAX).  ortho = ||G - I||_F, reported (an upper bound of the
+// spectral norm).  gate = 1 when the second orthonormalization must run: always for TWICE;
+// for AUTO when ||G - I||_2 > tol, decided exactly: ||G - I||_2 <= tol if and only if
+// (1 + tol) I - G and G - (1 - tol) I are positive semidefinite, tested (as definite) by
+// Cholesky; a Frobenius norm at or below tol settles it without the factorizations.
+__global__ __launch_bounds__(256) void k_ortho_gate(const double* __restrict__ G, int k, int mode,
+                                                    double tol, double* __restrict__ ortho_out,
+                                                    int* __restrict__ gate, tssvd_info* info) {
   __shared__ double red[256];
+  __shared__ double M[TSSVD_N_MAX * (TSSVD_N_MAX + 1) / 2];
   const int tid = threadIdx.x;
   double s = 0.0;
   for (int i = tid; i < k * k; i += 256) {
@@ -62,10 +94,20 @@ __global__ void k_ortho_gate(const double* __restrict__ G, int k, int mode, doub
     if (tid < w) red[tid] += red[tid + w];
     __syncthreads();
   }
+  const double o = sqrt(red[0]);
+  int g;
+  if (mode == TSSVD_ORTHO_TWICE) {
+    g = 1;
+  } else if (o <= tol) {
+    g = 0;
+  } else {
+    const bool upper = gate_chol_pd(M, G, k, -1.0, 1.0 + tol);  // (1 + tol) I - G
+    __syncthreads();
+    const bool lower = upper && gate_chol_pd(M, G, k, 1.0, 1.0 - tol);  // G - (1 - tol) I
+    g = !(upper && lower);
+  }
   if (tid == 0) {
-    const double o = sqrt(red[0]);
     *ortho_out = o;
-    const int g = (mode == TSSVD_ORTHO_TWICE) || !(o <= tol);
     *gate = g;
     if (info) {
       info->ortho = o;
@@ -79,18 +121,30 @@ __global__ void k_ortho_gate(const double* __restrict__ G, int k, int mode, doub
 // step k writes row k of R (G_kj / sqrt(G_kk)) and updates the trailing upper triangle,
 // G_ij -= G_ki G_kj / G_kk, on a 16 x 16 thread grid.  *bad = 1 when a pivot is not
 // positive and finite (then R is left unspecified).
+// With `dead` given (l flags, written), a pivot <= dead_tol G_kk (the squared sine of the
+// angle between column k of Y and the span of the earlier columns) drops direction k: row k
+// of R stays zero and there is no trailing update, so Y = Q R still holds with the dropped
+// column's coefficients in column k of R, and Q has no column k; dead[k] = 1 marks it.
 __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ G, int l,
-                                              double* __restrict__ R, int* __restrict__ bad) {
+                                              double* __restrict__ R, int* __restrict__ bad,
+                                              double dead_tol, int* __restrict__ dead) {
   extern __shared__ double Gs[];  // l x l, row-major
+  __shared__ unsigned char sdead[TSSVD_N_MAX];
   const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
   for (int i = tid; i < l * l; i += 256) {
     Gs[i] = G[i];
     R[i] = 0.0;
   }
+  for (int i = tid; i < l; i += 256) sdead[i] = 0;
   __syncthreads();
   int fail = 0;
   for (int k = 0; k < l; ++k) {
     const double piv = Gs[k * l + k];
+    if (dead && piv <= dead_tol * G[k * l + k]) {  // uniform, as below
+      if (tid == 0) sdead[k] = 1;
+      __syncthreads();
+      continue;
+    }
     if (!(piv > 0.0) || !isfinite(piv)) {  // uniform: every thread reads the same pivot
       fail = 1;
       break;
@@ -104,7 +158,19 @@ __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ G, int 
     }
     __syncthreads();
   }
+  if (dead)
+    for (int i = tid; i < l; i += 256) dead[i] = sdead[i];
   if (tid == 0) *bad = fail;
+}
+
+// Rm = R with each dropped direction's column replaced by e_k (row k of R is zero): the
+// nonsingular matrix whose inverse, with row k zeroed, maps Y to the kept basis.
+__global__ void k_unit_dead(const double* __restrict__ R, const int* __restrict__ dead, int l,
+                            double* __restrict__ Rm) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= l * l) return;
+  const int i = idx / l, j = idx - i * l;
+  Rm[idx] = dead[j] ? (i == j ? 1.0 : 0.0) : R[idx];
 }
 
 // Intermediate bases of the subspace iteration (Algorithm 5 before its last step) enter
@@ -436,7 +502,17 @@ __global__ void k_haar_fix(const double* __restrict__ Q, const double* __restric
 }
 
 struct TssvdWs {
-  TsqrPlan p;
+  TsqrPlan p;                      // float32 leaf plan on the mixed-precision route
+  // mixed: R1 (clamped); R2 = chol(Q1^T Q1) with kept columns, its unit-modified form and
+  // that form's inverse; the second pass's R2 (clamped), R3 (kept, unit-modified, inverse);
+  // Rtot, Ninv, N = Ninv P; the second pass's Gram; the solve's operand tiles and partial
+  // Grams
+  double *Rp = nullptr, *Rc = nullptr, *Rcm = nullptr, *Ri = nullptr, *Rp2 = nullptr;
+  double *R3 = nullptr, *R3m = nullptr, *R3i = nullptr, *Rtot = nullptr, *Ninv = nullptr;
+  double *Nm = nullptr, *G2 = nullptr, *op = nullptr, *pcpart = nullptr;
+  int* mflags = nullptr;  // mixed: [0] first Cholesky failed, [1] unused, [2] second pass,
+                          // [3] second Cholesky failed
+  int *mdead = nullptr, *mdead2 = nullptr;  // mixed: dropped directions per pass (n flags)
   TsqrPlan pn;                     // mixing: QR factorizations of n x n matrices
   double *Om, *Mm, *Mu, *Mv;       // mixing: Omega, R Omega^T, and the small SVD's factors
   double *Ut, *S, *Vt, *T, *P2, *S2, *W2, *V2, *G, *part, *ortho;
@@ -446,11 +522,37 @@ struct TssvdWs {
   size_t bytes;
 };
 
-TssvdWs tssvd_layout(int64_t m, int n, void* work) {
+// The mixed-precision tall-skinny route: A stored float32, 33 <= n (the float32 blocked
+// leaf), no discard rule, no mixing, not the Gram route.
+bool mixed_tssvd(const tssvd_opts& o, int32_t a_dtype, int64_t n) {
+  return o.prec == TSSVD_PREC_MIXED && a_dtype == TSSVD_F32 && n >= 33;
+}
+
+TssvdWs tssvd_layout(int64_t m, int n, void* work, bool mixed = false) {
   TssvdWs w;
   Carver c(work);
-  w.p = tsqr_plan(m, n);
+  w.p = tsqr_plan(m, n, 0, 0, mixed);
   tsqr_carve(w.p, c);
+  if (mixed) {
+    const size_t nn = (size_t)n * n;
+    w.Rp = c.take<double>(nn);
+    w.Rc = c.take<double>(nn);
+    w.Rcm = c.take<double>(nn);
+    w.Ri = c.take<double>(nn);
+    w.Rp2 = c.take<double>(nn);
+    w.R3 = c.take<double>(nn);
+    w.R3m = c.take<double>(nn);
+    w.R3i = c.take<double>(nn);
+    w.Rtot = c.take<double>(nn);
+    w.Ninv = c.take<double>(nn);
+    w.Nm = c.take<double>(nn);
+    w.G2 = c.take<double>(nn);
+    w.op = c.take<double>(pc_op_elems(n));
+    w.pcpart = c.take<double>((size_t)pc_grid(m) * nn);
+    w.mflags = c.take<int>(4);
+    w.mdead = c.take<int>((size_t)n);
+    w.mdead2 = c.take<int>((size_t)n);
+  }
   w.pn = tsqr_plan(n, n);
   tsqr_carve(w.pn, c);
   const size_t nn = (size_t)n * n;
@@ -533,6 +635,98 @@ hipError_t tssvd_gram(const void* A, int a_dtype, int64_t m, int ni, int64_t lda
   return hipGetLastError();
 }
 
+// Attributes for the one-workgroup Cholesky and triangular inverse at l up to
+// TSSVD_N_MAX (their l x l matrices exceed the default 64 KB of LDS).
+hipError_t chol_rinv_attrs() {
+  static bool attr_set = false;  // the attribute is per function; setting it twice is harmless
+  if (attr_set) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)k_rinv_gate,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     160 * 1024 - 8192);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          160 * 1024 - 8192);
+  if (e != hipSuccess) return e;
+  attr_set = true;
+  return hipSuccess;
+}
+
+// Mixed precision, Algorithm 2 with its first orthonormalization in float32 and its second
+// in float64 (A stored float32, 33 <= n <= TSSVD_N_MAX):
+//   1. TSQR of A with the blocked leaf in float32 arithmetic and the merge tree in float64:
+//      A ~ Q1 R1.  Householder's backward error is ~ eps_32 ||A|| per leaf chain (measured
+//      1e-6 .. 4e-6 ||A|| for 8 .. 61 blocks of 128 rows), so the float32 factors cannot
+//      give a residual ||A - U S V^T|| near float64 rounding; R1 serves as a preconditioner.
+//      ONCE returns this step: SVD R1 = U1~ S1 V1~^T, U = Q1 U1~ from the float32
+//      reflectors (orthonormal to ~1e-6).
+//   2. Q1 = A R1^-1 in float64 by a blocked triangular solve of the stored A (the paper's
+//      tall-skinny QR forms its Q as A R^-1), G = Q1^T Q1 fused; Q1 is written to U.
+//      A = Q1 R1 to float64 rounding (times the condition of R1's 16 x 16 diagonal blocks),
+//      and kappa(Q1) ~ 1 + eps_32 kappa(A) c.
+//   3. Second orthonormalization in float64 as a Cholesky QR of Q1: R2 = chol(G).  When the
+//      estimate sqrt(||G||_1) ||R2^-1||_F of kappa(R2) exceeds kPcKappa, once more on
+//      Q2 = Q1 R2^-1 (a second solve, in place in U) with R3 = chol(Q2^T Q2).
+//   4. SVD of R = R2 R1 (R3 R2 R1) = P S W^T by float64 Jacobi; V = W, U = Q (R^-1 P), Q the
+//      last stored basis, as a row-local product in place.
+// Rank deficiency: a diagonal entry of R1 below kPcClamp max|R1_ii| (a column float32 sees
+// as dependent) is raised to that size, which keeps Q1 bounded.  A column of Q1 dependent on
+// the earlier ones to float64 rounding (squared sine of its angle to their span at most
+// kMixedDeadSine2; a zero column) is dropped: its coefficients stay in R2, and the direction
+// comes out as an exact zero singular value (sigma = 0, zero column of U).  A nearly
+// dependent column stays; its large kappa(R2) calls the second Cholesky pass.
+// info->ortho reports ||Q1^T Q1 - I||_F and info->reorth = 1.
+constexpr double kMixedDeadSine2 = 1e-24;
+constexpr double kPcClamp = 0x1p-24;
+constexpr double kPcKappa = 64.0;
+
+hipError_t tssvd_mixed(const void* A, int64_t m, int ni, int64_t lda, double* U, int64_t ldu,
+                       double* S, double* V, int64_t ldv, tssvd_info* info, TssvdWs& w,
+                       const tssvd_opts& o, hipStream_t s, bool prof) {
+  const int64_t n = ni;
+  const unsigned nb = (unsigned)((ni * ni + 255) / 256);
+  hipError_t e;
+#define MTRY(x) do { e = (x); if (e != hipSuccess) return e; } while (0)
+  MTRY(tsqr_factor(w.p, A, TSSVD_F32, lda, s, prof));
+  if (o.ortho == TSSVD_ORTHO_ONCE) {
+    MTRY(jacobi_svd(tsqr_root(w.p), ni, ni, 1, 0.0, o.max_jacobi_sweeps, 1, w.Vt, w.S, w.Ut,
+                    info, s));
+    MTRY(tsqr_apply(w.p, w.Ut, ni, U, ldu, s, prof));
+    MTRY(copy_matrix(w.S, 1, ni, ni, S, ni, s));
+    MTRY(copy_matrix(w.Vt, n, ni, n, V, ldv, s));
+    return hipGetLastError();
+  }
+  MTRY(pc_trsm_gram(tsqr_root(w.p), ni, ni, kPcClamp, w.Rp, w.op, A, TSSVD_F32, lda, m, U,
+                    ldu, w.pcpart, w.G, nullptr, s));                   // Q1 -> U, G
+  hipLaunchKernelGGL(k_ortho_gate, dim3(1), dim3(256), 0, s, w.G, ni, (int)TSSVD_ORTHO_TWICE,
+                     o.reorth_tol, w.ortho, w.gate, info);               // gate = 1
+  MTRY(chol_rinv_attrs());
+  const size_t lds = (size_t)ni * ni * sizeof(double);
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), lds, s, w.G, ni, w.Rc, w.mflags,
+                     kMixedDeadSine2, w.mdead);                         // R2 (kept columns)
+  hipLaunchKernelGGL(k_unit_dead, dim3(nb), dim3(256), 0, s, w.Rc, w.mdead, ni, w.Rcm);
+  hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), lds, s, w.Rcm, ni, 1e300, w.Ri,
+                     w.mflags + 1, (const int*)nullptr);
+  MTRY(pc_kappa_flag(w.G, w.Ri, ni, kPcKappa, w.mflags + 2, s));
+  // second pass Q2 = Q1 R2m^-1, gated on mflags[2] (its preparation, reduction and small
+  // steps always run)
+  MTRY(pc_trsm_gram(w.Rcm, ni, ni, kPcClamp, w.Rp2, w.op, U, TSSVD_F64, ldu, m, U, ldu,
+                    w.pcpart, w.G2, w.mflags + 2, s));
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), lds, s, w.G2, ni, w.R3, w.mflags + 3,
+                     kMixedDeadSine2, w.mdead2);
+  hipLaunchKernelGGL(k_unit_dead, dim3(nb), dim3(256), 0, s, w.R3, w.mdead2, ni, w.R3m);
+  hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), lds, s, w.R3m, ni, 1e300, w.R3i,
+                     w.mflags + 1, (const int*)nullptr);
+  MTRY(pc_combine(w.mflags, w.Rp, w.Rc, w.Rp2, w.Ri, w.R3, w.R3i, w.mdead, w.mdead2, ni,
+                  w.Rtot, w.Ninv, info, s));
+  MTRY(jacobi_svd(w.Rtot, ni, ni, 1, 0.0, o.max_jacobi_sweeps, 1, w.Vt, w.S, w.Ut, info, s));
+  hipLaunchKernelGGL(k_small_gemm, dim3(nb), dim3(256), 0, s, w.Ninv, w.Ut, ni, w.Nm, w.gate);
+  MTRY(pc_rowmul(U, ldu, m, ni, w.Nm, ni, w.op, nullptr, s));          // U = Q Ninv P
+  MTRY(copy_matrix(w.S, 1, ni, ni, S, ni, s));
+  MTRY(copy_matrix(w.Vt, n, ni, n, V, ldv, s));
+#undef MTRY
+  return hipGetLastError();
+}
+
 }  // namespace
 
 extern "C" {
@@ -601,8 +795,8 @@ int tssvd_workspace_bytes(int64_t m, int64_t n, int32_t a_dtype, const tssvd_opt
                           size_t* bytes) {
   if (!bytes || bad_dtype(a_dtype) || n < 1 || m < n) return TSSVD_E_INVALID_ARG;
   if (n > TSSVD_N_MAX) return TSSVD_E_UNSUPPORTED;
-  (void)opts;
-  *bytes = tssvd_layout(m, (int)n, nullptr).bytes;
+  const tssvd_opts o = resolve(opts);
+  *bytes = tssvd_layout(m, (int)n, nullptr, mixed_tssvd(o, a_dtype, n)).bytes;
   return TSSVD_OK;
 }
 
@@ -628,13 +822,21 @@ int tssvd_run(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
   if (check_opts(o) != TSSVD_OK) return TSSVD_E_INVALID_ARG;
   if (n > TSSVD_N_MAX) return TSSVD_E_UNSUPPORTED;
   const int ni = (int)n;
-  TssvdWs w = tssvd_layout(m, ni, work);
+  const bool mixed = mixed_tssvd(o, a_dtype, n);
+  if (o.prec == TSSVD_PREC_MIXED) {
+    if (a_dtype != TSSVD_F32) return TSSVD_E_INVALID_ARG;
+    if (!mixed || o.working_precision > 0.0 || (o.flags & (TSSVD_FLAG_MIX | TSSVD_FLAG_GRAM)))
+      return TSSVD_E_UNSUPPORTED;
+  }
+  TssvdWs w = tssvd_layout(m, ni, work, mixed);
   if (!work || work_bytes < w.bytes) return TSSVD_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
 
   const bool mix = (o.flags & TSSVD_FLAG_MIX) != 0;
   if (mix && (o.flags & TSSVD_FLAG_GRAM)) return TSSVD_E_INVALID_ARG;
   TRY(info_init(info, s));
+  if (mixed)
+    return hip_status(tssvd_mixed(A, m, ni, lda, U, ldu, S, V, ldv, info, w, o, s, prof));
   if (o.flags & TSSVD_FLAG_GRAM)
     return hip_status(tssvd_gram(A, a_dtype, m, ni, lda, U, ldu, S, V, ldv, info, w, o, s));
   // Algorithm 1: TSQR A = Q R; SVD R = U~ S V~^T (discard rule inside); U = Q U~.
@@ -676,7 +878,7 @@ int tssvd_run(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
   // TWICE; for AUTO when ||U^T U - I||_F > reorth_tol.  The host cannot read the gate
   // without a synchronization, so the pass is always enqueued and every kernel of it
   // returns at once when the gate is 0.
-  TRY(gemm_atq_f64(U, TSSVD_F64, ldu, m, n, U, (int)ldu, ni, w.G, ni, w.part, s));
+  TRY(gram_any(U, TSSVD_F64, ldu, m, ni, w.G, ni, w.part, s));
   hipLaunchKernelGGL(k_ortho_gate, dim3(1), dim3(256), 0, s, w.G, ni, o.ortho, o.reorth_tol,
                      w.ortho, w.gate, info);
   TsqrPlan p2 = w.p;
@@ -731,7 +933,8 @@ int tssvd_noalloc(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t 
       ldv < n)
     return TSSVD_E_INVALID_ARG;
   if (n > TSSVD_N_MAX) return TSSVD_E_UNSUPPORTED;
-  if (tssvd_layout(m, (int)n, nullptr).bytes > (size_t)TSSVD_NOALLOC_SCRATCH_BYTES)
+  const bool mixed = mixed_tssvd(resolve(opts), a_dtype, n);
+  if (tssvd_layout(m, (int)n, nullptr, mixed).bytes > (size_t)TSSVD_NOALLOC_SCRATCH_BYTES)
     return TSSVD_E_UNSUPPORTED;
   void* work = nullptr;
   const int st = scratch_address(&work);
@@ -874,16 +1077,8 @@ hipError_t basis_via_r(const TsqrPlan& p, double* Y, int64_t rows, int l, const 
   const double kmax = (wp > 0.0) ? 0.0 : kKappaMax;
   hipError_t e = gemm_atq_f64(Y, TSSVD_F64, l, rows, l, Y, l, l, G, l, part, s);  // Y^T Y
   if (e != hipSuccess) return e;
-  static bool attr_set = false;  // the attribute is per function; setting it twice is harmless
-  if (!attr_set) {
-    e = hipFuncSetAttribute((const void*)k_rinv_gate,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024 - 8192);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  e = chol_rinv_attrs();
+  if (e != hipSuccess) return e;
   if (l <= 16) {
     hipLaunchKernelGGL(k_chol_rinv_gate<16>, dim3(1), dim3(64), 0, s, G, l, kmax, T, use_q,
                        chol_bad);
@@ -895,7 +1090,7 @@ hipError_t basis_via_r(const TsqrPlan& p, double* Y, int64_t rows, int l, const 
                        chol_bad);
   } else {
     hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), (size_t)l * l * sizeof(double), s, G, l, Rc,
-                       chol_bad);
+                       chol_bad, 0.0, (int*)nullptr);
     hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), (size_t)l * l * sizeof(double),
                        s, Rc, l, kmax, T, use_q, chol_bad);
   }

@@ -472,8 +472,90 @@ __global__ __launch_bounds__(256) void k_gram_f64(const TY* __restrict__ Y, int6
       }
 }
 
-static int gram_grid(int64_t rows, int64_t& chunk) {
-  int64_t want = (rows + 63) / 64;
+// 65 <= l <= 16*NT <= 128: the NT(NT+1)/2 tiles are dealt to the four waves (tile t to wave
+// t % 4), and every wave sums its tiles over all rows of the workgroup's chunk, so no
+// cross-wave sum is needed and a wave holds at most ceil(NTILE/4) accumulator tiles.  Each
+// wave loads every four-row group itself (the other waves' loads of it hit the L1).
+template <int NT, int W, typename TY>
+__device__ __forceinline__ void gram_wave_tiles(const TY* __restrict__ Y, int64_t r0, int64_t r1,
+                                                int l, int ldy, double* __restrict__ P) {
+  constexpr int NTILE = NT * (NT + 1) / 2;
+  constexpr int PER = (NTILE - W + 3) / 4;  // tiles W, W+4, ...
+  const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  // tile number -> (ti, tj), ti <= tj, in the order of k_gram_f64
+  auto tile_i = [](int t) constexpr {
+    int ti = 0;
+    while (t >= NT - ti) { t -= NT - ti; ++ti; }
+    return ti;
+  };
+  auto tile_j = [](int t) constexpr {
+    int ti = 0;
+    while (t >= NT - ti) { t -= NT - ti; ++ti; }
+    return ti + t;
+  };
+  f64x4 acc[PER > 0 ? PER : 1];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  auto load = [&](int64_t grp, double (&y)[NT]) {
+    const int64_t row = r0 + 4 * grp + g;
+    const bool ok = row < r1;
+    const TY* yr = Y + (ok ? row : r0) * ldy;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int col = 16 * t + li;
+      const double v = (double)yr[col < l ? col : l - 1];
+      y[t] = (ok && col < l) ? v : 0.0;
+    }
+  };
+  const int64_t ngrp = (r1 - r0 + 3) / 4;
+  double y0[NT], y1[NT];
+  load(0, y0);
+  load(1, y1);
+  for (int64_t gb = 0; gb < ngrp; gb += 2) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+      acc[q] = mfma_f64(y0[tile_i(W + 4 * q)], y0[tile_j(W + 4 * q)], acc[q]);
+    load(gb + 2, y0);  // groups past the chunk load zeros
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+      acc[q] = mfma_f64(y1[tile_i(W + 4 * q)], y1[tile_j(W + 4 * q)], acc[q]);
+    load(gb + 3, y1);
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int ti = tile_i(W + 4 * q), tj = tile_j(W + 4 * q);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * ti + 4 * r + g, j = 16 * tj + li;
+      if (i <= j && j < l) {
+        P[(int64_t)i * l + j] = acc[q][r];
+        P[(int64_t)j * l + i] = acc[q][r];
+      }
+    }
+  }
+}
+
+template <int NT, typename TY = double>
+__global__ __launch_bounds__(256) void k_gram_f64w(const TY* __restrict__ Y, int64_t rows,
+                                                   int l, int ldy, int64_t chunk,
+                                                   double* __restrict__ part) {
+  const int wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = (r0 + chunk < rows) ? r0 + chunk : rows;
+  double* P = part + (int64_t)blockIdx.x * l * l;
+  switch (wave) {
+    case 0: gram_wave_tiles<NT, 0>(Y, r0, r1, l, ldy, P); break;
+    case 1: gram_wave_tiles<NT, 1>(Y, r0, r1, l, ldy, P); break;
+    case 2: gram_wave_tiles<NT, 2>(Y, r0, r1, l, ldy, P); break;
+    default: gram_wave_tiles<NT, 3>(Y, r0, r1, l, ldy, P); break;
+  }
+}
+
+// Workgroups (row chunks) of the Gram kernels.  Never more chunks than the A^T Q kernels
+// use for the same shape (atq_grid: ceil(rows/64) up to l = 64, ceil(rows/256) beyond), so
+// the partials fit in the atq_partials(rows, l, l) doubles callers provide.
+static int gram_grid(int64_t rows, int l, int64_t& chunk) {
+  int64_t want = l <= 64 ? (rows + 63) / 64 : (rows + 255) / 256;
   if (want > GRAM_WG_MAX) want = GRAM_WG_MAX;
   chunk = (rows + want - 1) / want;
   chunk = (chunk + 15) / 16 * 16;
@@ -484,12 +566,16 @@ template <typename TY>
 static hipError_t gram_f64(const TY* Y, int64_t rows, int l, int ldy, double* G, int ldg,
                            double* part, hipStream_t s) {
   int64_t chunk;
-  const int nwg = gram_grid(rows, chunk);
+  const int nwg = gram_grid(rows, l, chunk);
   switch ((l + 15) / 16) {
     case 1: hipLaunchKernelGGL((k_gram_f64<1, TY>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
     case 2: hipLaunchKernelGGL((k_gram_f64<2, TY>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
     case 3: hipLaunchKernelGGL((k_gram_f64<3, TY>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
     case 4: hipLaunchKernelGGL((k_gram_f64<4, TY>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
+    case 5: hipLaunchKernelGGL((k_gram_f64w<5, TY>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
+    case 6: hipLaunchKernelGGL((k_gram_f64w<6, TY>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
+    case 7: hipLaunchKernelGGL((k_gram_f64w<7, TY>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
+    case 8: hipLaunchKernelGGL((k_gram_f64w<8, TY>), dim3(nwg), dim3(256), 0, s, Y, rows, l, ldy, chunk, part); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
@@ -555,7 +641,7 @@ size_t column_sumsq_partials(int64_t rows, int l) {
 // split-K A^T Q kernel with Q = Y otherwise.  `part` holds atq_partials(rows, l, l) doubles.
 hipError_t gram_any(const void* Y, int y_dtype, int64_t ldy, int64_t rows, int l, double* G,
                     int ldg, double* part, hipStream_t s) {
-  if (l <= 64)
+  if (l <= 128)
     return (y_dtype == TSSVD_F64)
                ? gram_f64((const double*)Y, rows, l, (int)ldy, G, ldg, part, s)
                : gram_f64((const float*)Y, rows, l, (int)ldy, G, ldg, part, s);
@@ -574,7 +660,7 @@ hipError_t gram_any(const void* Y, int y_dtype, int64_t ldy, int64_t rows, int l
 hipError_t gemm_atq_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int64_t n,
                         const double* Q, int ldq, int l, double* Z, int ldz, double* part,
                         hipStream_t s, int prof) {
-  if (a_dtype == TSSVD_F64 && A == (const void*)Q && lda == ldq && n == l && l <= 64 && m > 0)
+  if (a_dtype == TSSVD_F64 && A == (const void*)Q && lda == ldq && n == l && l <= 128 && m > 0)
     return gram_f64(Q, m, l, ldq, Z, ldz, part, s);  // partials fit: nwg <= atq chunks
   prof_begin(prof, s);
   hipError_t e = (a_dtype == TSSVD_F64)

@@ -49,13 +49,16 @@ struct TsqrPlan {
   // reflector tails V (256 x 16 ntw), the panel factors T_p and the products Z_cp = V_c^T V_p.
   // Vleaf then points at Vwy (callers use it as m x n scratch) and tauleaf is unused.
   int ntw = 0;
-  double* Vwy = nullptr;
-  double* Twy = nullptr;
-  double* Zwy = nullptr;
+  bool wyf32 = false;  // blocked leaf in float32 arithmetic and storage (V, T_p, Z_cp)
+  void* Vwy = nullptr;
+  void* Twy = nullptr;
+  void* Zwy = nullptr;
 };
 
 // nr (8 or 16, narrow tiles only) and wtarget (leaf workgroups) override the defaults.
-TsqrPlan tsqr_plan(int64_t m, int n, int nr = 0, int wtarget = 0);
+// leaf_f32: the blocked leaf (33 <= n <= 128) computes in float32 (wyf32); the merge tree
+// stays float64.  For n < 33 the flag is ignored (check p.wyf32).
+TsqrPlan tsqr_plan(int64_t m, int n, int nr = 0, int wtarget = 0, bool leaf_f32 = false);
 void tsqr_carve(TsqrPlan& p, Carver& c);
 // Factor: leaf blocks + tree.  After it, root R (n x n, upper, row-major) is tsqr_root(p).
 hipError_t tsqr_factor(const TsqrPlan& p, const void* A, int a_dtype, int64_t lda,
@@ -69,8 +72,8 @@ hipError_t tsqr_apply(const TsqrPlan& p, const double* S, int k, double* out, in
 // Blocked leaf kernels (csrc/tsqr_wy.hip), used by tsqr_factor / tsqr_apply when ntw > 0.
 hipError_t wy_factor(const TsqrPlan& p, const void* A, int a_dtype, int64_t lda, hipStream_t s);
 hipError_t wy_apply(const TsqrPlan& p, int k, double* out, int64_t ldo, hipStream_t s);
-// doubles of storage per 256-row block: V, the ntw panel factors T_p and the Z_cp pairs
-size_t wy_block_doubles(int ntw);
+// elements of storage per block: V, the ntw panel factors T_p and the Z_cp pairs
+size_t wy_block_elems(int ntw);
 
 // ------------------------------------------------------------------ small SVD (Jacobi)
 // SVD of M (n x n row-major, stride ldm; its transpose when transpose != 0):
@@ -150,6 +153,32 @@ hipError_t gemm_atq_bf16c(const void* Ac, int64_t m, int64_t n, const void* Qp, 
 hipError_t gemm_atq_mixed(const float* A, int64_t lda, int64_t m, int64_t n, const void* Qp,
                           int l, double* Z, int ldz, double* part, int kind, hipStream_t s,
                           int prof = -1);
+
+// ------------------------------------------------------------------ preconditioned Cholesky QR
+// (csrc/precond.hip; 33 <= n <= 112)
+// Rp = R with diagonal entries below tol max|R_ii| raised to that size; Q = X Rp^-1 (X m x n
+// float32 or float64, stride ldx; Q float64, stride ldq, may be X itself for float64) and
+// G = Q^T Q (n x n).  Rop: pc_op_elems(n) doubles; part: pc_grid(m) n n doubles.  With a
+// gate, the solve runs only if *gate != 0 (the preparation and the reduction always run).
+int pc_grid(int64_t m);
+size_t pc_op_elems(int n);
+hipError_t pc_trsm_gram(const double* R, int ldr, int n, double tol, double* Rp, double* Rop,
+                        const void* X, int x_dtype, int64_t ldx, int64_t m, double* Q,
+                        int64_t ldq, double* part, double* G, const int* gate, hipStream_t s);
+// X <- X N in place (X m x n float64, stride ldx; N n x n, stride ldn); Nop: pc_op_elems(n).
+hipError_t pc_rowmul(double* X, int64_t ldx, int64_t m, int n, const double* N, int ldn,
+                     double* Nop, const int* gate, hipStream_t s);
+// *flag = 1 when sqrt(||G||_1) ||Ri||_F > kmax (an upper bound of kappa_2 of G's Cholesky
+// factor, Ri its inverse) or not finite.
+hipError_t pc_kappa_flag(const double* G, const double* Ri, int n, double kmax, int* flag,
+                         hipStream_t s);
+// fl[2] != 0: Rtot = R3 R2b Rp, Ninv = R3^-1; else Rtot = R2 Rp, Ninv = R2^-1; rows of a
+// dropped direction (flags d2, resp. d1) zeroed in both; fl[0] / fl[3] (failed Cholesky
+// factorizations) set NUM_NONFINITE in info.
+hipError_t pc_combine(const int* fl, const double* Rp, const double* R2, const double* R2b,
+                      const double* R2i, const double* R3, const double* R3i, const int* d1,
+                      const int* d2, int n, double* Rtot, double* Ninv, tssvd_info* info,
+                      hipStream_t s);
 
 // ------------------------------------------------------------------ reverse pass
 hipError_t bw_svd_core(const double* Ub, const double* sig, const double* G1, const double* G2,

@@ -354,7 +354,7 @@ static void pick_tile(int n, int& nc, int& nr, int& tnr) {
   else { nc = 8; nr = 8; tnr = 8; }
 }
 
-TsqrPlan tsqr_plan(int64_t m, int n, int nr, int wtarget) {
+TsqrPlan tsqr_plan(int64_t m, int n, int nr, int wtarget, bool leaf_f32) {
   TsqrPlan p;
   p.m = m;
   p.n = n;
@@ -367,13 +367,15 @@ TsqrPlan tsqr_plan(int64_t m, int n, int nr, int wtarget) {
   if (n >= 33 && n <= 128) {
     p.ntw = (n + 15) / 16;
     p.B = 128;
+    p.wyf32 = leaf_f32;
   }
   p.nblocks = (m + p.B - 1) / p.B;
   // About as many leaf workgroups as can be resident at once (two per CU for the wide
   // tiles, four for the narrow ones, one for the blocked leaf): fewer would idle CUs, more
   // would only deepen the merge tree.
-  const int64_t target = wtarget > 0 ? wtarget : p.ntw ? (p.ntw <= 7 ? 512 : 256)
-                                                        : (p.nc >= 4) ? 512 : 1024;
+  const int64_t target = wtarget > 0 ? wtarget
+                         : p.ntw ? (p.ntw <= 7 || p.wyf32 ? 512 : 256)
+                                 : (p.nc >= 4) ? 512 : 1024;
   int64_t W = p.nblocks < target ? p.nblocks : target;
   p.bpw = (int)((p.nblocks + W - 1) / W);
   p.W = (int)((p.nblocks + p.bpw - 1) / p.bpw);
@@ -389,10 +391,20 @@ void tsqr_carve(TsqrPlan& p, Carver& c) {
   const int n = p.n;
   if (p.ntw) {
     const int nt = p.ntw;
-    p.Vwy = c.take<double>((size_t)p.nblocks * p.B * 16 * nt);
-    p.Twy = c.take<double>((size_t)p.nblocks * nt * 256);
-    p.Zwy = c.take<double>((size_t)p.nblocks * (nt > 1 ? nt * (nt - 1) / 2 : 1) * 256);
-    p.Vleaf = p.Vwy;
+    const size_t nv = (size_t)p.nblocks * p.B * 16 * nt;
+    const size_t ntt = (size_t)p.nblocks * nt * 256;
+    const size_t nz = (size_t)p.nblocks * (nt > 1 ? nt * (nt - 1) / 2 : 1) * 256;
+    if (p.wyf32) {
+      p.Vwy = c.take<float>(nv);
+      p.Twy = c.take<float>(ntt);
+      p.Zwy = c.take<float>(nz);
+      p.Vleaf = nullptr;  // no float64 m x n scratch in a float32 plan
+    } else {
+      p.Vwy = c.take<double>(nv);
+      p.Twy = c.take<double>(ntt);
+      p.Zwy = c.take<double>(nz);
+      p.Vleaf = (double*)p.Vwy;
+    }
     p.tauleaf = nullptr;
   } else {
     p.Vleaf = c.take<double>((size_t)p.nblocks * n * p.B);

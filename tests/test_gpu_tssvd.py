@@ -79,6 +79,26 @@ def test_auto_mode_measures_and_skips():
     assert sigma_rel(S2, S) < 1e-13 and np.max(col_sin(U2, U)) < 1e-10
 
 
+@pytest.mark.parametrize("m,n", [(20000, 100), (30000, 48)])
+def test_auto_gate_tests_the_spectral_norm(m, n):
+    """The AUTO gate decides on ||U^T U - I||_2 (by Cholesky tests of (1 + tol) I - G and
+    G - (1 - tol) I), not on the reported Frobenius norm: a tolerance between the two skips the
+    second pass (U bitwise that of ONCE), one below the spectral norm runs it."""
+    A = _graded(m, n, seed=21)
+    U1, S1, V1, _ = _run(A, ortho=T.ORTHO_ONCE)
+    E = U1.T @ U1 - np.eye(n)
+    spec, frob = float(np.linalg.norm(E, 2)), float(np.linalg.norm(E))
+    flush_print(f"case gate m={m} n={n}: ||E||_2 {spec:.2e}  ||E||_F {frob:.2e}")
+    assert frob > 2.0 * spec  # room for a tolerance strictly between them
+    tol = (spec * frob) ** 0.5
+    U, S, V, info = _run(A, ortho=T.ORTHO_AUTO, reorth_tol=tol)
+    assert info["reorth"] == 0 and info["ortho"] > tol
+    assert np.array_equal(U, U1) and np.array_equal(S, S1)
+    U2, S2, V2, info2 = _run(A, ortho=T.ORTHO_AUTO, reorth_tol=spec / 3.0)
+    assert info2["reorth"] == 1
+    assert checks.ortho_spec(U2) < 1e-13 and sigma_rel(S2, S1) < 1e-13
+
+
 def test_rank_deficient_zero_columns():
     """Exactly rank-deficient input, wp = 0: the nonzero part matches; no NaN."""
     A = _graded(2000, 12, seed=9)
@@ -90,6 +110,9 @@ def test_rank_deficient_zero_columns():
     assert sigma_rel(S[:10], Sr[:10]) < 1e-12
     assert S[10] < 1e-14 * S[0] and S[11] < 1e-14 * S[0]
     assert info["numstat"] == 0
+    live = S > 0
+    assert np.all(U[:, ~live] == 0)  # an exact zero sigma has a zero left vector
+    assert checks.ortho_spec(U[:, live]) < 1e-13 and checks.ortho_spec(V[:, live]) < 1e-13
 
 
 def test_discard_rule_matches_oracle():
@@ -129,12 +152,16 @@ def test_deterministic_bitwise():
 
 @pytest.mark.parametrize("m,n", [(128, 128), (5000, 7), (70001, 100), (33, 33), (255, 40),
                                  (256, 48), (257, 64), (3001, 97), (20000, 113),
-                                 (600001, 100), (70001, 128)])
+                                 (600001, 100), (70001, 128), (5000, 128), (4999, 64)])
 def test_tsqr_factor_vs_householder(m, n):
     """R equals LAPACK's Householder R up to row signs; Q R = A; Q^T Q = I.  The shapes
-    with n >= 33 run the blocked leaf (256-row blocks, 16-column panels): one partial block,
+    with n >= 33 run the blocked leaf (128-row blocks, 16-column panels): one partial block,
     exactly one block and one row past it, a last panel holding one real column (n = 97,
-    113), and chains of several blocks per workgroup (m = 70,001 and 600,001)."""
+    113), and chains of several blocks per workgroup (m = 70,001 and 600,001).  m = 5000 and
+    4999 end in a block of 8 and 7 rows that starts a chain, so its columns past the 8th are
+    rounding residue that shrinks by the unit roundoff with each use of the 8-row space and
+    squares to subnormal numbers on the way to zero (the reflector scalars must stay finite
+    there)."""
     flush_print("case tsqr", m, n)
     A = _graded(m, n, seed=m + n)
     Q, R = T.tsqr(dev(A))
