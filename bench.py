@@ -14,7 +14,8 @@ Also reported, in the same line:
                 recorded on the library's stream inside the timed region
   cpu_baseline  the float64 CPU oracle (host cores) on a row sample of the same matrix
   legs          randomized SVD 200,000 x 2,000 float64; tall-skinny SVD 10,000 x 20 and
-                4,000,000 x 100 (float64 and float32 storage)
+                4,000,000 x 100 (float64 storage; float32 storage on the float64 and the
+                mixed-precision routes, with the speedup of the latter)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--legs w1,w2,w3]
 """
@@ -429,7 +430,8 @@ def leg_tssvd(workload, steps, warmup, dtype_name=None, ortho=None, prec=None, A
                sigma_rel_err_vs_planted=srel,
                leaf_factor_ms=round(lf[0] / lf[1], 4), leaf_apply_ms=round(la[0] / la[1], 4),
                leaf_factor_gbs=round(abytes / lf_s / 1e9, 2) if lf[0] else None,
-               leaf_factor_fp64_tflops=round(2.0 * m * n * n / lf_s / 1e12, 3) if lf[0] else None)
+               leaf_factor_tflops=round(2.0 * m * n * n / lf_s / 1e12, 3) if lf[0] else None)
+    out["_S"] = S.cpu().numpy()
     del U, work
     torch.cuda.empty_cache()
     return out
@@ -620,6 +622,7 @@ def main():
         try:
             if leg == "w1":
                 legs["w1"] = leg_tssvd(1, max(args.steps, 20), args.warmup)
+                legs["w1"].pop("_S")
             elif leg == "w2":
                 s2, A2 = generate(2)
                 r2 = run_lowrank(A2, s2, T.PREC_FP64, args.steps, args.warmup, 2)
@@ -637,10 +640,19 @@ def main():
                 legs["w3_f64"] = leg_tssvd(3, args.steps, args.warmup, A=A3)
                 legs["w3_f64_once"] = leg_tssvd(3, args.steps, args.warmup, A=A3,
                                                 ortho=T.ORTHO_ONCE)
+                legs["w3_f64"].pop("_S")
+                legs["w3_f64_once"].pop("_S")
                 del A3
                 torch.cuda.empty_cache()
                 _, A3 = generate(3, "f32")
-                legs["w3_f32_storage_fp64"] = leg_tssvd(3, args.steps, args.warmup, A=A3)
+                f64 = leg_tssvd(3, args.steps, args.warmup, A=A3)
+                mx = leg_tssvd(3, args.steps, args.warmup, A=A3, prec=T.PREC_MIXED)
+                s64, smx = f64.pop("_S"), mx.pop("_S")
+                mx["sigma_max_abs_diff_vs_fp64_over_sigma1"] = float(
+                    np.max(np.abs(smx - s64)) / s64[0])
+                mx["speedup_vs_fp64_same_bytes"] = round(f64["ms_per_call"] / mx["ms_per_call"], 3)
+                legs["w3_f32_storage_fp64"] = f64
+                legs["w3_mixed"] = mx
                 del A3
                 torch.cuda.empty_cache()
         except Exception as e:  # a failing secondary leg is reported, not fatal

@@ -68,16 +68,16 @@ typedef enum {
                                 TSQR, small SVD and the second orthonormalization in
                                 float64.  tssvd (33 <= n; no discard rule, mixing or
                                 Gram route, else TSSVD_E_UNSUPPORTED): Algorithm 2 with
-                                its first orthonormalization in float32 (TSQR leaf
-                                reflectors, their matrix-core products and U1 = Q1 U1~;
-                                merge tree and small SVD in float64) and its second in
-                                float64 (Cholesky QR of the float32 U1: U = U1 R2^-1 P);
-                                AUTO runs the second pass always, ONCE returns U1.
-                                For exactly rank-deficient A the first pass can lose
-                                a direction (a column of U1 with norm under 0.03 after
-                                the earlier ones are taken out): the second pass drops
-                                it as an exact zero singular value (sigma = 0, zero
-                                column of U).                                          */
+                                its first factorization A = Q1 R1 from a float32 TSQR
+                                (leaf reflectors and their matrix-core products in
+                                float32, merge tree in float64) whose Q1 is formed as
+                                A R1^-1 by a float64 triangular solve, and its second
+                                Q1 = Q R2 as a float64 Cholesky QR (repeated once when
+                                R2 is ill-conditioned); T = R2 R1 = P S W^T, U = Q P.
+                                ONCE returns U = Q1~ U1~ from the float32 Householder
+                                reflectors (orthonormal to ~1e-6).  A direction that
+                                is exactly dependent (to float64 rounding) comes out as
+                                sigma = 0 with a zero column of U.                     */
 } tssvd_prec;
 
 typedef enum {

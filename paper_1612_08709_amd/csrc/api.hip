@@ -175,7 +175,7 @@ __global__ void k_unit_dead(const double* __restrict__ R, const int* __restrict_
 
 // Intermediate bases of the subspace iteration (Algorithm 5 before its last step) enter
 // only through products with A, and Q = Y R^-1 spans the same space as the TSQR's
-// Householder Q (the paper's own TSQR formed Q = A R^-1).  With T = R^-1 the m x l basis
+// Householder Q.  With T = R^-1 the m x l basis
 // need not be formed by the reverse Householder pass.  Rounding in Y R^-1 grows with
 // kappa(R); when the Frobenius estimate ||R||_F ||R^-1||_F exceeds kappa_max (or R^-1 is
 // not finite, e.g. for a rank-deficient sketch) the kernel sets *use_q = 1 and T = I, and
@@ -659,11 +659,13 @@ hipError_t chol_rinv_attrs() {
 //      give a residual ||A - U S V^T|| near float64 rounding; R1 serves as a preconditioner.
 //      ONCE returns this step: SVD R1 = U1~ S1 V1~^T, U = Q1 U1~ from the float32
 //      reflectors (orthonormal to ~1e-6).
-//   2. Q1 = A R1^-1 in float64 by a blocked triangular solve of the stored A (the paper's
-//      tall-skinny QR forms its Q as A R^-1), G = Q1^T Q1 fused; Q1 is written to U.
+//   2. Q1 = A R1^-1 in float64 by a blocked triangular solve of the stored A, so that
+//      A = Q1 R1 is the first factorization of Algorithm 2 (with Q1 only nearly
+//      orthonormal); G = Q1^T Q1 fused; Q1 is written to U.
 //      A = Q1 R1 to float64 rounding (times the condition of R1's 16 x 16 diagonal blocks),
 //      and kappa(Q1) ~ 1 + eps_32 kappa(A) c.
-//   3. Second orthonormalization in float64 as a Cholesky QR of Q1: R2 = chol(G).  When the
+//   3. Algorithm 2's second factorization Q1 = Q R2 in float64, as a Cholesky QR of Q1:
+//      R2 = chol(G) (T = R2 R1 as in the algorithm).  When the
 //      estimate sqrt(||G||_1) ||R2^-1||_F of kappa(R2) exceeds kPcKappa, once more on
 //      Q2 = Q1 R2^-1 (a second solve, in place in U) with R3 = chol(Q2^T Q2).
 //   4. SVD of R = R2 R1 (R3 R2 R1) = P S W^T by float64 Jacobi; V = W, U = Q (R^-1 P), Q the

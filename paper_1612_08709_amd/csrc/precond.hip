@@ -3,9 +3,9 @@
 //   Q1 = A R1^-1     (blocked triangular solve in float64, A read as stored),
 //   G  = Q1^T Q1     (fused into the same pass),
 // and, after the Cholesky factor R2 of G, U = Q1 (R2^-1 P) by a row-local product.
-// The paper's tall-skinny QR forms its Q as A R^-1 (Section 2's reduction); here R comes
-// from a lower-precision factorization, so Q1 is only nearly orthonormal and the second
-// orthonormalization (Algorithm 2) is a Cholesky QR of Q1 in float64.
+// A = Q1 R1 is then the first factorization of Algorithm 2 with a Q1 that is only nearly
+// orthonormal (R1 comes from a lower-precision factorization), and the algorithm's second
+// factorization Q1 = Q R2 is a Cholesky QR of Q1 in float64.
 //
 // Matrix-core layout (v_mfma_f64_16x16x4_f64): lane (i = lane % 16, g = lane / 16) supplies
 // a[i][k] and b[k][i] for k = g in each 4-deep instruction; the result register r holds
