@@ -548,75 +548,10 @@ def run_probe():
     print(json.dumps(res))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--legs", default="w1,w2,w3,w5")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=250_000)
-    ap.add_argument("--calib-copy", action="store_true",
-                    help="run one 1 GiB read + 1 GiB write elementwise kernel first (counter "
-                         "calibration for the HBM traffic figures)")
-    ap.add_argument("--simple-data", action="store_true",
-                    help="Gaussian matrices instead of planted spectra (hardware-counter runs)")
-    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="print the traffic profile from two rocprofv3 --pmc output folders "
-                         "(FETCH_SIZE, WRITE_SIZE) and exit")
-    ap.add_argument("--summarize-trace", metavar="DIR",
-                    help="print a summary of a rocprofv3 --kernel-trace --stats folder and exit")
-    ap.add_argument("--by-grid", metavar="REGEX",
-                    help="with --summarize-trace: also list the launches of the matching "
-                         "kernels by grid size")
-    ap.add_argument("--command", default="",
-                    help="the profiling command, recorded in a summary")
-    ap.add_argument("--probe", action="store_true",
-                    help="measure the MFMA, FMA and HBM ceilings (bench_probe.hip) and exit")
-    args = ap.parse_args()
-    if args.probe:
-        run_probe()
-        return
-    if args.summarize_pmc:
-        print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.command))
-        return
-    if args.summarize_trace:
-        print(summarize_trace(args.summarize_trace, args.command, args.by_grid))
-        return
-    global SIMPLE_DATA
-    SIMPLE_DATA = args.simple_data
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the library runs on a single GPU).", file=sys.stderr)
-        sys.exit(2)
+def run_legs(args):
+    """The secondary legs named in --legs (a failing leg is reported, not fatal)."""
     import torch
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
     import paper_1612_08709_amd as T
-    if args.calib_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
-
-    spec, A = generate(4)
-    mixed = run_lowrank(A, spec, T.PREC_MIXED, args.steps, args.warmup, 4)
-    fp64 = run_lowrank(A, spec, T.PREC_FP64, max(2, args.steps // 2), 1, 4)
-    sig_diff = float(np.max(np.abs(mixed["S"] - fp64["S"]) / fp64["S"]))
-    # the paper's other method on the same bytes: Algorithm 8 (Gram-based bases), mixed
-    gram = run_lowrank(A, spec, T.PREC_MIXED, max(2, args.steps // 2), 1, 4, flags=T.FLAG_GRAM)
-    gram_sig_diff = float(np.max(np.abs(gram["S"] - fp64["S"]) / fp64["S"]))
-    # Section 3's cheaper tracking: LU bases in the power steps, mixed
-    lu = run_lowrank(A, spec, T.PREC_MIXED, max(2, args.steps // 2), 1, 4, flags=T.FLAG_LU)
-    lu_sig_diff = float(np.max(np.abs(lu["S"] - fp64["S"]) / fp64["S"]))
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline_lowrank(A, mixed["Om"], spec, min(args.cpu_rows, spec["m"]))
-    del A
-    torch.cuda.empty_cache()
-
     legs = {}
     for leg in [x for x in args.legs.split(",") if x]:
         try:
@@ -657,6 +592,85 @@ def main():
                 torch.cuda.empty_cache()
         except Exception as e:  # a failing secondary leg is reported, not fatal
             legs[leg] = dict(error=repr(e))
+    return legs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--legs", default="w1,w2,w3,w5")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--legs-only", action="store_true",
+                    help="run only the legs named in --legs and print them (profiling aid; "
+                         "not the benchmark line)")
+    ap.add_argument("--cpu-rows", type=int, default=250_000)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB read + 1 GiB write elementwise kernel first (counter "
+                         "calibration for the HBM traffic figures)")
+    ap.add_argument("--simple-data", action="store_true",
+                    help="Gaussian matrices instead of planted spectra (hardware-counter runs)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the traffic profile from two rocprofv3 --pmc output folders "
+                         "(FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="print a summary of a rocprofv3 --kernel-trace --stats folder and exit")
+    ap.add_argument("--by-grid", metavar="REGEX",
+                    help="with --summarize-trace: also list the launches of the matching "
+                         "kernels by grid size")
+    ap.add_argument("--command", default="",
+                    help="the profiling command, recorded in a summary")
+    ap.add_argument("--probe", action="store_true",
+                    help="measure the MFMA, FMA and HBM ceilings (bench_probe.hip) and exit")
+    args = ap.parse_args()
+    if args.probe:
+        run_probe()
+        return
+    if args.summarize_pmc:
+        print(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.command))
+        return
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace, args.command, args.by_grid))
+        return
+    global SIMPLE_DATA
+    SIMPLE_DATA = args.simple_data
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the library runs on a single GPU).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    import paper_1612_08709_amd as T
+    if args.legs_only:
+        print(json.dumps({"legs": run_legs(args)}))
+        return
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    spec, A = generate(4)
+    mixed = run_lowrank(A, spec, T.PREC_MIXED, args.steps, args.warmup, 4)
+    fp64 = run_lowrank(A, spec, T.PREC_FP64, max(2, args.steps // 2), 1, 4)
+    sig_diff = float(np.max(np.abs(mixed["S"] - fp64["S"]) / fp64["S"]))
+    # the paper's other method on the same bytes: Algorithm 8 (Gram-based bases), mixed
+    gram = run_lowrank(A, spec, T.PREC_MIXED, max(2, args.steps // 2), 1, 4, flags=T.FLAG_GRAM)
+    gram_sig_diff = float(np.max(np.abs(gram["S"] - fp64["S"]) / fp64["S"]))
+    # Section 3's cheaper tracking: LU bases in the power steps, mixed
+    lu = run_lowrank(A, spec, T.PREC_MIXED, max(2, args.steps // 2), 1, 4, flags=T.FLAG_LU)
+    lu_sig_diff = float(np.max(np.abs(lu["S"] - fp64["S"]) / fp64["S"]))
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_lowrank(A, mixed["Om"], spec, min(args.cpu_rows, spec["m"]))
+    del A
+    torch.cuda.empty_cache()
+
+    legs = run_legs(args)
 
     cbytes = spec["m"] * (64 * ((spec["n"] + 63) // 64)) * 2
     a_streamed = (3 * mixed["abytes"] + (2 * spec["q"] - 1) * cbytes + cbytes

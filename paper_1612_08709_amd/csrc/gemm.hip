@@ -551,6 +551,118 @@ __global__ __launch_bounds__(256) void k_gram_f64w(const TY* __restrict__ Y, int
   }
 }
 
+// 33 <= l <= 16*NT <= 128, staged: 64-row chunks go to the workgroups in turn (chunk c to
+// workgroup c mod gridDim.x, a fixed order per partial).  A chunk is loaded four rows per
+// pass, 64 consecutive threads per row (coalesced), into registers while the previous chunk
+// is summed, then stored to the local data share (padding columns as zeros).  Each wave sums
+// its share of the NT(NT+1)/2 tile pairs over the 64 rows, both operands read from the
+// staged rows (contraction over rows: lane (i, g) supplies row 4q + g of tile columns i).
+constexpr int GS_CH = 64;
+template <int NT>
+constexpr int gs_ld() { return 16 * NT + 2; }
+template <int NT>
+constexpr size_t gs_lds() { return (size_t)GS_CH * gs_ld<NT>() * sizeof(double); }
+
+template <int NT, typename TY>
+__global__ __launch_bounds__(256, 2) void k_gram_staged(const TY* __restrict__ Y, int64_t rows,
+                                                        int l, int ldy,
+                                                        double* __restrict__ part) {
+  constexpr int NTT = NT * (NT + 1) / 2;
+  constexpr int NPW = (NTT + 3) / 4;
+  constexpr int SLD = gs_ld<NT>();
+  constexpr int CPR = (16 * NT + 63) / 64;  // 64-column slices per row
+  constexpr int PASSES = GS_CH / 4;         // four rows per pass, 64 threads per row
+  extern __shared__ double Sb[];  // GS_CH x SLD
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  // thread t stages row 4 pass + t / 64, columns t % 64 + 64 c (padding past l: zeros)
+  const int prow = tid >> 6, pcol = tid & 63;
+  const int64_t nch = (rows + GS_CH - 1) / GS_CH;
+  double pre[PASSES][CPR];
+  auto load = [&](int64_t ch) {
+    const int64_t r0 = ch * GS_CH + prow;
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps) {
+      const int64_t row = r0 + 4 * ps;
+      const TY* yr = Y + (row < rows ? row : 0) * (int64_t)ldy;
+#pragma unroll
+      for (int c = 0; c < CPR; ++c) {
+        const int col = pcol + 64 * c;
+        pre[ps][c] = (row < rows && col < l) ? (double)yr[col] : 0.0;
+      }
+    }
+  };
+  f64x4 acc[NPW];
+#pragma unroll
+  for (int p = 0; p < NPW; ++p) acc[p] = f64x4{0.0, 0.0, 0.0, 0.0};
+  int tp[NPW], tq[NPW];
+#pragma unroll
+  for (int p = 0; p < NPW; ++p) {
+    int t = wave + 4 * p, a = 0;
+    if (t >= NTT) t = 0;  // unused slot (not summed)
+    while (t >= NT - a) {
+      t -= NT - a;
+      ++a;
+    }
+    tp[p] = a;
+    tq[p] = a + t;
+  }
+  if (blockIdx.x < nch) load(blockIdx.x);
+  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    __syncthreads();  // the previous chunk's sums have read the staged rows
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps)
+#pragma unroll
+      for (int c = 0; c < CPR; ++c) {
+        const int col = pcol + 64 * c;
+        if (col < 16 * NT) Sb[(4 * ps + prow) * SLD + col] = pre[ps][c];
+      }
+    __syncthreads();
+    if (ch + gridDim.x < nch) load(ch + gridDim.x);
+#pragma unroll
+    for (int p = 0; p < NPW; ++p) {
+      if (wave + 4 * p < NTT) {
+        const int ci = 16 * tp[p] + li, cj = 16 * tq[p] + li;
+#pragma unroll
+        for (int q = 0; q < GS_CH / 4; ++q) {
+          const double* srow = Sb + (4 * q + g) * SLD;
+          acc[p] = mfma_f64(srow[ci], srow[cj], acc[p]);
+        }
+      }
+    }
+  }
+  double* P = part + (int64_t)blockIdx.x * l * l;
+#pragma unroll
+  for (int p = 0; p < NPW; ++p) {
+    if (wave + 4 * p < NTT) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * tp[p] + 4 * r + g, j = 16 * tq[p] + li;
+        if (i <= j && j < l) {  // diagonal tiles: the entry i <= j for both places
+          P[(int64_t)i * l + j] = acc[p][r];
+          P[(int64_t)j * l + i] = acc[p][r];
+        }
+      }
+    }
+  }
+}
+
+template <int NT, typename TY>
+static hipError_t launch_gram_staged(const TY* Y, int64_t rows, int l, int ldy, int nwg,
+                                     double* part, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_gram_staged<NT, TY>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)gs_lds<NT>());
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_gram_staged<NT, TY>), dim3(nwg), dim3(256), gs_lds<NT>(), s, Y, rows, l,
+                     ldy, part);
+  return hipGetLastError();
+}
+
 // Workgroups (row chunks) of the Gram kernels.  Never more chunks than the A^T Q kernels
 // use for the same shape (atq_grid: ceil(rows/64) up to l = 64, ceil(rows/256) beyond), so
 // the partials fit in the atq_partials(rows, l, l) doubles callers provide.
@@ -565,6 +677,29 @@ static int gram_grid(int64_t rows, int l, int64_t& chunk) {
 template <typename TY>
 static hipError_t gram_f64(const TY* Y, int64_t rows, int l, int ldy, double* G, int ldg,
                            double* part, hipStream_t s) {
+  if (l >= 33) {
+    // staged kernel: at most 512 workgroups and never more than the partials callers
+    // provide (the A^T Q chunk count for this shape)
+    int ncol, nck;
+    int64_t cr;
+    atq_grid(rows, l, ncol, nck, cr);
+    const int64_t nch = (rows + GS_CH - 1) / GS_CH;
+    int64_t nwg = nch < 512 ? nch : 512;
+    if (nwg > nck) nwg = nck;
+    if (nwg < 1) nwg = 1;
+    hipError_t e;
+    switch ((l + 15) / 16) {
+      case 3: e = launch_gram_staged<3>(Y, rows, l, ldy, (int)nwg, part, s); break;
+      case 4: e = launch_gram_staged<4>(Y, rows, l, ldy, (int)nwg, part, s); break;
+      case 5: e = launch_gram_staged<5>(Y, rows, l, ldy, (int)nwg, part, s); break;
+      case 6: e = launch_gram_staged<6>(Y, rows, l, ldy, (int)nwg, part, s); break;
+      case 7: e = launch_gram_staged<7>(Y, rows, l, ldy, (int)nwg, part, s); break;
+      case 8: e = launch_gram_staged<8>(Y, rows, l, ldy, (int)nwg, part, s); break;
+      default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    return reduce_chunks(part, (int)nwg, l, l, G, ldg, s);
+  }
   int64_t chunk;
   const int nwg = gram_grid(rows, l, chunk);
   switch ((l + 15) / 16) {

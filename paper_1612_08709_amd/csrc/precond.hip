@@ -229,9 +229,9 @@ __global__ __launch_bounds__(PC_THREADS, 1) void k_pc_trsm(
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * P + 4 * r + g, j = 16 * C + li;
-        if (i < n && j < n) {
+        if (i <= j && j < n) {  // diagonal tiles: the entry i <= j for both places
           pw[(int64_t)i * n + j] = gacc[p][r];
-          if (P != C) pw[(int64_t)j * n + i] = gacc[p][r];
+          pw[(int64_t)j * n + i] = gacc[p][r];
         }
       }
     }
