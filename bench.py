@@ -247,6 +247,66 @@ def summarize_pmc(fetch_dir, write_dir, command):
     return "\n".join(lines)
 
 
+def summarize_mfma(d, command, title):
+    """Markdown summary of one rocprofv3 --pmc run with the derived metrics MfmaUtil,
+    MfmaFlopsF64 / F32 / BF16 (SQ_INSTS_VALU_MFMA_MOPS_* x 512) and, from the kernel trace
+    of the same run, each dispatch's duration: per library kernel the median matrix-core
+    flops per dispatch, the achieved rate and the matrix-core busy share."""
+    import csv
+    import glob
+    import statistics
+    rows = _pmc_rows(d)
+    per_dispatch = {}
+    for r in rows:
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        rec = per_dispatch.setdefault(key, {"name": r["Kernel_Name"]})
+        rec[r["Counter_Name"]] = rec.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    dur = {}
+    for path in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+                dur[key] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    by_kernel = {}
+    for key, rec in per_dispatch.items():
+        if "tsv::" not in rec["name"]:
+            continue
+        name = rec["name"].replace("(anonymous namespace)::", "").split("(")[0]
+        name = name.replace("void ", "")
+        by_kernel.setdefault(name, []).append((rec, dur.get(key)))
+    lines = [f"# Matrix-core counters per dispatch: {title}", "",
+             "Command (from the repository root):", "", "```", command, "```", "",
+             "MfmaUtil = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs) x 100; "
+             "MfmaFlops* = SQ_INSTS_VALU_MFMA_MOPS_* x 512 (rocprofv3 derived metrics); "
+             "duration from the kernel trace of the same run.  Medians over dispatches "
+             "(launches under 20 us that a device gate turned off are left out).", "",
+             "| kernel | dispatches | median us | MFMA GFLOP per dispatch (f64 / f32 / bf16) | "
+             "achieved TFLOP/s | MfmaUtil % |", "|---|---|---|---|---|---|"]
+    out = {}
+    for name, lst in sorted(by_kernel.items(), key=lambda kv: -sum((t or 0) for _, t in kv[1])):
+        # launches that return at once (a device gate off) are left out of the medians
+        if any((t or 0) >= 20e-6 for _, t in lst):
+            lst = [(rec, t) for rec, t in lst if (t or 0) >= 20e-6]
+        ts = [t for _, t in lst if t]
+        fl = {k: statistics.median([rec.get(f"MfmaFlops{k}", 0.0) for rec, _ in lst])
+              for k in ("F64", "F32", "BF16")}
+        util = statistics.median([rec.get("MfmaUtil", 0.0) for rec, _ in lst])
+        tot = sum(fl.values())
+        tmed = statistics.median(ts) if ts else None
+        rate = tot / tmed / 1e12 if (tmed and tot) else 0.0
+        if tot == 0 and (tmed or 0) < 50e-6:
+            continue  # short kernels without matrix-core work
+        out[name] = dict(dispatches=len(lst), median_us=round(tmed * 1e6, 1) if tmed else None,
+                         gflop_f64=round(fl["F64"] / 1e9, 3), gflop_f32=round(fl["F32"] / 1e9, 3),
+                         gflop_bf16=round(fl["BF16"] / 1e9, 3), tflops=round(rate, 2),
+                         mfma_util_pct=round(util, 1))
+        lines.append(f"| `{name}` | {len(lst)} | {out[name]['median_us']} | "
+                     f"{fl['F64'] / 1e9:.2f} / {fl['F32'] / 1e9:.2f} / {fl['BF16'] / 1e9:.2f} | "
+                     f"{rate:.1f} | {util:.1f} |")
+    lines += ["", "mfma-json: " + json.dumps(out)]
+    return "\n".join(lines)
+
+
 def traffic_of(name):
     """Scaled HBM bytes per launch of a kernel, or None if absent or the source changed."""
     try:
@@ -614,6 +674,10 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the traffic profile from two rocprofv3 --pmc output folders "
                          "(FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--summarize-mfma", nargs=2, metavar=("DIR", "TITLE"),
+                    help="print the matrix-core counter summary of a rocprofv3 --pmc run "
+                         "(MfmaUtil MfmaFlopsF64 MfmaFlopsF32 MfmaFlopsBF16, with "
+                         "--kernel-trace) and exit")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="print a summary of a rocprofv3 --kernel-trace --stats folder and exit")
     ap.add_argument("--by-grid", metavar="REGEX",
@@ -632,6 +696,9 @@ def main():
         return
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.command, args.by_grid))
+        return
+    if args.summarize_mfma:
+        print(summarize_mfma(args.summarize_mfma[0], args.command, args.summarize_mfma[1]))
         return
     global SIMPLE_DATA
     SIMPLE_DATA = args.simple_data
