@@ -483,25 +483,50 @@ __global__ __launch_bounds__(WTHREADS, 2) void k_wy_factor(
   }
 }
 
-// Apply: one workgroup per leaf chain, one wave per 16-column tile of the output (k
-// columns).  The seed S (n x k, row-major, float64) of the chain comes from the merge tree.
-template <typename CT, int NT, typename OT>
-__global__ __launch_bounds__(64 * 8) void k_wy_apply(
+// Apply: one workgroup of 8 waves per leaf chain, blocks from the chain's last to its
+// first.  The seed S (n x k, k <= n, row-major, float64) of the chain comes from the merge
+// tree.  Per block, two phases:
+//   1. W = T S by the panel recurrence W_p = T_p (S_p - sum_{q>p} Z_pq W_q): wave c
+//      (c < ceil(k/16)) takes output columns 16c .. 16c+15 and keeps its seed tiles in
+//      registers (S <- S - W afterwards).  A W tile in result layout is, lane for lane, the
+//      B operand of the product below, so it goes to the local data share as it stands.
+//   2. The block's rows of U = -V W: wave t takes rows 16t .. 16t+15 (each row of V read
+//      once, as A operands) and all output tiles, W read from the local data share.
+// The wave's V rows are loaded before phase 1, so their latency hides behind it.  With ZS
+// (when it fits) the block's T_p and Z_cp tiles are staged in the local data share too:
+// the next block's are copied in at the end of phase 2, so the recurrence reads no global
+// memory.
+constexpr int WA_WAVES = WB / 16;  // 8: one row tile per wave in phase 2
+template <typename CT, int NT>
+constexpr size_t wa_lds(bool zs) {
+  return ((size_t)NT * NT + (zs ? (size_t)NT * (NT + 1) / 2 : 0)) * 256 * sizeof(CT);
+}
+template <typename CT, int NT>
+constexpr bool wa_zs() { return wa_lds<CT, NT>(true) <= 160 * 1024; }
+
+template <typename CT, int NT, typename OT, bool ZS>
+__global__ __launch_bounds__(64 * WA_WAVES) void k_wy_apply(
     const CT* __restrict__ Vg, const CT* __restrict__ Tg, const CT* __restrict__ Zg,
     const double* __restrict__ Sw, int n, int k, int bpw, int64_t nblocks, int64_t m,
     OT* __restrict__ out, int64_t ldo, const int* __restrict__ gate) {
   using L = Wy<CT>;
   using v4 = typename L::v4;
   if (gate && *gate == 0) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, g = lane >> 4;
   constexpr int NPAIR = NT * (NT - 1) / 2;
+  constexpr int NZT = NPAIR + NT;  // staged tiles: the Z_cp pairs, then T_0 .. T_{NT-1}
+  extern __shared__ __attribute__((aligned(16))) char wa_smem[];
+  // [q][J][s][lane] = W[16q + row(s, g)][16J + i]
+  CT* Wl = reinterpret_cast<CT*>(wa_smem);
+  CT* ZTl = Wl + NT * NT * 256;  // ZS: the block's Z_cp then T_p tiles (global layout)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
   constexpr int LDV = 16 * NT;
   const CT zero = CT(0);
-  const int np = (n + 15) >> 4;  // panels in use
+  const int np = (n + 15) >> 4;   // panels in use
+  const int ncw = (k + 15) >> 4;  // output column tiles (<= np)
+  const bool cwave = wave < ncw;
   const int col = 16 * wave + li;
-  const bool cok = col < k;
-  // seed tile q, result layout: s[q][r] = S[16q + row(r, g)][col]
+  // seed tile q of a column wave, result layout: s[q][r] = S[16q + row(r, g)][col]
   CT s[NT][4];
   const double* S = Sw + (int64_t)blockIdx.x * n * k;
 #pragma unroll
@@ -509,62 +534,93 @@ __global__ __launch_bounds__(64 * 8) void k_wy_apply(
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * q + L::row(r, g);
-      s[q][r] = (cok && row < n) ? (CT)S[(int64_t)row * k + col] : zero;
+      s[q][r] = (cwave && col < k && row < n) ? (CT)S[(int64_t)row * k + col] : zero;
     }
   const int64_t b0 = (int64_t)blockIdx.x * bpw;
   const int64_t b1 = (b0 + bpw < nblocks) ? b0 + bpw : nblocks;
+  auto stage_zt = [&](int64_t blk) {
+    const CT* Zb = Zg + blk * (int64_t)(NPAIR > 0 ? NPAIR : 1) * 256;
+    const CT* Tb = Tg + blk * (int64_t)NT * 256;
+    for (int i = tid; i < NZT * 256; i += 64 * WA_WAVES)
+      ZTl[i] = (i < NPAIR * 256) ? Zb[i] : Tb[i - NPAIR * 256];
+  };
+  if constexpr (ZS) {
+    if (b1 > b0) stage_zt(b1 - 1);
+    __syncthreads();
+  }
   for (int64_t blk = b1 - 1; blk >= b0; --blk) {
     const CT* Vb = Vg + blk * (int64_t)WB * LDV;
-    const CT* Tb = Tg + blk * (int64_t)NT * 256;
-    const CT* Zb = Zg + blk * (int64_t)(NPAIR > 0 ? NPAIR : 1) * 256;
-    // W_p = T_p (S_p - sum_{q>p} Z_pq W_q), last panel first
-    CT wq[NT][4];
+    const CT* Zb = ZS ? ZTl : Zg + blk * (int64_t)(NPAIR > 0 ? NPAIR : 1) * 256;
+    const CT* Tb = ZS ? ZTl + NPAIR * 256 : Tg + blk * (int64_t)NT * 256;
+    // this wave's rows of V (phase 2), as A operands: row 16 wave + i, 16-column group q
+    CT va[NT][4];
+    {
+      const CT* vr = Vb + (int64_t)(16 * wave + li) * LDV + 4 * g;
 #pragma unroll
-    for (int q = NT - 1; q >= 0; --q) {
-      if (q >= np) {
+      for (int q = 0; q < NT; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) wq[q][r] = zero;
-        continue;
-      }
-      v4 acc = {s[q][0], s[q][1], s[q][2], s[q][3]};
-#pragma unroll
-      for (int q2 = q + 1; q2 < NT; ++q2) {
-        if (q2 >= np) continue;
-        const CT* zr = Zb + (int64_t)upair(q, q2, NT) * 256 + li * 16 + 4 * g;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc = L::mma(-zr[t], wq[q2][t], acc);
-      }
-      const CT* tr = Tb + (int64_t)q * 256 + li * 16 + 4 * g;
-      v4 wv = {zero, zero, zero, zero};
-#pragma unroll
-      for (int t = 0; t < 4; ++t) wv = L::mma(tr[t], acc[t], wv);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) wq[q][r] = wv[r];
+        for (int t = 0; t < 4; ++t) va[q][t] = (q < np) ? vr[16 * q + t] : zero;
     }
-    // rows of U: -V W, 16 rows per tile
-    for (int rt = 0; rt < WB / 16; ++rt) {
-      const int64_t row0 = blk * WB + 16 * rt;
-      if (row0 >= m) break;
-      v4 u = {zero, zero, zero, zero};
-      const CT* vr = Vb + (int64_t)(16 * rt + li) * LDV + 4 * g;
+    // ---- phase 1: W = T S, last panel first
+    if (cwave) {
+      CT wq[NT][4];
 #pragma unroll
-      for (int q = 0; q < NT; ++q) {
-        if (q >= np) continue;
+      for (int q = NT - 1; q >= 0; --q) {
+        if (q >= np) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) u = L::mma(vr[16 * q + t], wq[q][t], u);
+          for (int r = 0; r < 4; ++r) wq[q][r] = zero;
+        } else {
+          v4 acc = {s[q][0], s[q][1], s[q][2], s[q][3]};
+#pragma unroll
+          for (int q2 = q + 1; q2 < NT; ++q2) {
+            if (q2 >= np) continue;
+            const CT* zr = Zb + upair(q, q2, NT) * 256 + li * 16 + 4 * g;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc = L::mma(-zr[t], wq[q2][t], acc);
+          }
+          const CT* tr = Tb + q * 256 + li * 16 + 4 * g;
+          v4 wv = {zero, zero, zero, zero};
+#pragma unroll
+          for (int t = 0; t < 4; ++t) wv = L::mma(tr[t], acc[t], wv);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) wq[q][r] = wv[r];
+        }
       }
-      if (cok) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t row = row0 + L::row(r, g);
-          if (row < m) out[row * ldo + col] = (OT)(-u[r]);
+          Wl[((q * NT + wave) * 4 + r) * 64 + lane] = wq[q][r];
+          s[q][r] -= wq[q][r];
+        }
+    }
+    __syncthreads();
+    // ---- phase 2: rows 16 wave .. 16 wave + 15 of U = -V W
+    const int64_t row0 = blk * WB + 16 * wave;
+    if (row0 < m) {
+      for (int J = 0; J < ncw; ++J) {
+        v4 u = {zero, zero, zero, zero};
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+          if (q >= np) continue;
+          const CT* wl = Wl + (q * NT + J) * 256 + lane;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) u = L::mma(va[q][t], wl[64 * t], u);
+        }
+        const int c = 16 * J + li;
+        if (c < k) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t row = row0 + L::row(r, g);
+            if (row < m) out[row * ldo + c] = (OT)(-u[r]);
+          }
         }
       }
     }
-#pragma unroll
-    for (int q = 0; q < NT; ++q)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) s[q][r] -= wq[q][r];
+    if constexpr (ZS) {
+      if (blk > b0) stage_zt(blk - 1);  // phase 1 of this block has read the staged tiles
+    }
+    __syncthreads();  // before the next block's phase 1 reads them and overwrites W
   }
 }
 
@@ -606,8 +662,16 @@ static hipError_t wy_factor_launch(const TsqrPlan& p, const void* A, int a_dtype
 template <typename CT, int NT, typename OT>
 static hipError_t wy_apply_launch(const TsqrPlan& p, int k, OT* out, int64_t ldo,
                                   hipStream_t s) {
-  const int waves = (k + 15) / 16;
-  hipLaunchKernelGGL((k_wy_apply<CT, NT, OT>), dim3(p.W), dim3(64 * waves), 0, s,
+  constexpr bool ZS = wa_zs<CT, NT>();
+  const size_t lds = wa_lds<CT, NT>(ZS);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_wy_apply<CT, NT, OT, ZS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_wy_apply<CT, NT, OT, ZS>), dim3(p.W), dim3(64 * WA_WAVES), lds, s,
                      (const CT*)p.Vwy, (const CT*)p.Twy, (const CT*)p.Zwy, p.Slev[0], p.n, k,
                      p.bpw, p.nblocks, p.m, out, ldo, p.gate);
   return hipGetLastError();
@@ -629,7 +693,7 @@ static hipError_t wy_factor_ct(const TsqrPlan& p, const void* A, int a_dtype, in
 
 template <typename CT, typename OT>
 static hipError_t wy_apply_ct(const TsqrPlan& p, int k, OT* out, int64_t ldo, hipStream_t s) {
-  if (k < 1 || k > 128) return hipErrorInvalidValue;
+  if (k < 1 || k > 16 * p.ntw) return hipErrorInvalidValue;  // W holds ntw x ntw tiles
   switch (p.ntw) {
     case 3: return wy_apply_launch<CT, 3>(p, k, out, ldo, s);
     case 4: return wy_apply_launch<CT, 4>(p, k, out, ldo, s);
