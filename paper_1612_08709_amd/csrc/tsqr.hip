@@ -371,10 +371,10 @@ TsqrPlan tsqr_plan(int64_t m, int n, int nr, int wtarget, bool leaf_f32) {
   }
   p.nblocks = (m + p.B - 1) / p.B;
   // About as many leaf workgroups as can be resident at once (two per CU for the wide
-  // tiles, four for the narrow ones, one for the blocked leaf): fewer would idle CUs, more
-  // would only deepen the merge tree.
+  // tiles and the float64 blocked leaf, four for the float32 blocked leaf and the narrow
+  // tiles): fewer would idle CUs, more would only deepen the merge tree.
   const int64_t target = wtarget > 0 ? wtarget
-                         : p.ntw ? (p.ntw <= 7 || p.wyf32 ? 512 : 256)
+                         : p.ntw ? (p.wyf32 ? 1024 : p.ntw <= 7 ? 512 : 256)
                                  : (p.nc >= 4) ? 512 : 1024;
   int64_t W = p.nblocks < target ? p.nblocks : target;
   p.bpw = (int)((p.nblocks + W - 1) / W);

@@ -200,7 +200,8 @@ __host__ __device__ constexpr int upair(int c, int q, int nt) { return c * nt - 
 
 // Column tiles per contraction round (partials staged in the local data share).  With
 // float64 and n <= 112 the shared state stays under 80 KB, so two workgroups share a CU and
-// each hides the other's barrier waits and block loads.
+// each hides the other's barrier waits and block loads; in float32 (half the registers and
+// shared state) four do.
 template <int NT>
 constexpr int wch() { return NT <= 4 ? NT - 1 : 2; }
 
@@ -224,7 +225,7 @@ size_t wy_factor_lds() { return sizeof(WyShared<CT, NT>); }
 // operand-permuted), all in the compute type; per workgroup the final R (n x n row-major,
 // zero below the diagonal, float64).
 template <typename CT, int NT, typename TA>
-__global__ __launch_bounds__(WTHREADS, 2) void k_wy_factor(
+__global__ __launch_bounds__(WTHREADS, sizeof(CT) == 4 ? 4 : 2) void k_wy_factor(
     const TA* __restrict__ A, int64_t lda, int64_t m, int n, int bpw, int64_t nblocks,
     CT* __restrict__ Vg, CT* __restrict__ Tg, CT* __restrict__ Zg, double* __restrict__ Rw,
     const int* __restrict__ gate) {
