@@ -16,8 +16,9 @@
  *   - Every matrix/vector pointer is a DEVICE pointer owned by the caller.  The library
  *     never allocates device or host memory and never synchronizes the stream: all work
  *     is enqueued on `stream` (a hipStream_t; NULL = the legacy default stream).
- *   - Scratch memory is the caller's `work` buffer (device, 256-byte aligned), sized by
- *     the matching *_workspace_bytes query.  Its contents are undefined on return.
+ *   - Scratch memory is the caller's `work` buffer (device, 256-byte aligned, else
+ *     TSSVD_E_WORKSPACE), sized by the matching *_workspace_bytes query.  Its contents are
+ *     undefined on return.
  *   - Inputs A may be float64 or float32 (a_dtype).  Outputs U, S, V are float64.
  *   - Return value: a tssvd_status for errors detectable on the host (checked before
  *     any work is enqueued; nothing is enqueued on error).  Numerical conditions found

@@ -661,7 +661,7 @@ hipError_t chol_rinv_attrs() {
 //      reflectors (orthonormal to ~1e-6).
 //   2. Q1 = A R1^-1 in float64 by a blocked triangular solve of the stored A, so that
 //      A = Q1 R1 is the first factorization of Algorithm 2 (with Q1 only nearly
-//      orthonormal); G = Q1^T Q1 fused; Q1 is written to U.
+//      orthonormal); Q1 is written to U and G = Q1^T Q1 formed by the staged Gram kernel.
 //      A = Q1 R1 to float64 rounding (times the condition of R1's 16 x 16 diagonal blocks),
 //      and kappa(Q1) ~ 1 + eps_32 kappa(A) c.
 //   3. Algorithm 2's second factorization Q1 = Q R2 in float64, as a Cholesky QR of Q1:
@@ -698,7 +698,8 @@ hipError_t tssvd_mixed(const void* A, int64_t m, int ni, int64_t lda, double* U,
     return hipGetLastError();
   }
   MTRY(pc_trsm_gram(tsqr_root(w.p), ni, ni, kPcClamp, w.Rp, w.op, A, TSSVD_F32, lda, m, U,
-                    ldu, w.pcpart, w.G, nullptr, s));                   // Q1 -> U, G
+                    ldu, w.pcpart, w.G, nullptr, s, false));            // Q1 -> U
+  MTRY(gram_any(U, TSSVD_F64, ldu, m, ni, w.G, ni, w.part, s));        // G = Q1^T Q1
   hipLaunchKernelGGL(k_ortho_gate, dim3(1), dim3(256), 0, s, w.G, ni, (int)TSSVD_ORTHO_TWICE,
                      o.reorth_tol, w.ortho, w.gate, info);               // gate = 1
   MTRY(chol_rinv_attrs());
@@ -730,6 +731,12 @@ hipError_t tssvd_mixed(const void* A, int64_t m, int ni, int64_t lda, double* U,
 }
 
 }  // namespace
+
+// The workspace must start on 256 bytes (the kernels read their packed operands from it
+// with 16-byte vector loads).
+static bool misaligned(const void* work) {
+  return (reinterpret_cast<uintptr_t>(work) & 255) != 0;
+}
 
 extern "C" {
 
@@ -777,7 +784,7 @@ int tsqr(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda, doub
   if (n > TSSVD_TSQR_N_MAX) return TSSVD_E_UNSUPPORTED;
   size_t need = 0;
   tsqr_workspace_bytes(m, n, a_dtype, &need);
-  if (!work || work_bytes < need) return TSSVD_E_WORKSPACE;
+  if (!work || work_bytes < need || misaligned(work)) return TSSVD_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   TsqrPlan p = tsqr_plan(m, (int)n);
   Carver c(work);
@@ -831,7 +838,7 @@ int tssvd_run(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t lda,
       return TSSVD_E_UNSUPPORTED;
   }
   TssvdWs w = tssvd_layout(m, ni, work, mixed);
-  if (!work || work_bytes < w.bytes) return TSSVD_E_WORKSPACE;
+  if (!work || work_bytes < w.bytes || misaligned(work)) return TSSVD_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
 
   const bool mix = (o.flags & TSSVD_FLAG_MIX) != 0;
@@ -1165,7 +1172,7 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
   const int ki = (int)k, li = (int)l;
   const bool acopy = mixed && q >= 1 && !(o.flags & TSSVD_FLAG_NO_A_COPY);
   LowrankWs w = lowrank_layout(m, n, ki, li, work, mixed, acopy);
-  if (!work || work_bytes < w.bytes) return TSSVD_E_WORKSPACE;
+  if (!work || work_bytes < w.bytes || misaligned(work)) return TSSVD_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
 
   TRY(info_init(info, s));
@@ -1384,7 +1391,7 @@ int lowrank_svd_backward(const void* A, int32_t a_dtype, int64_t m, int64_t n, i
   (void)U; (void)S; (void)V;  // the forward is recomputed from (A, Omega); see the header
   const int ki = (int)k, li = (int)l, qi = (int)q;
   BackwardWs w = backward_layout(m, n, ki, li, qi, work);
-  if (!work || work_bytes < w.bytes) return TSSVD_E_WORKSPACE;
+  if (!work || work_bytes < w.bytes || misaligned(work)) return TSSVD_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   const int K2 = w.K2;
   const size_t ll = (size_t)li * li;

@@ -33,6 +33,40 @@ __device__ __forceinline__ d4 mma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Four adjacent elements of a row (a lane's share of a tile): one vector access when the
+// caller has checked 16-byte alignment of the rows (VEC), else element by element.
+template <bool VEC>
+__device__ __forceinline__ void ld4(const float* p, bool ok, d4& v) {
+  if (VEC) {
+    const float4 x = ok ? *reinterpret_cast<const float4*>(p) : float4{0.f, 0.f, 0.f, 0.f};
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = ok ? (double)p[r] : 0.0;
+  }
+}
+template <bool VEC>
+__device__ __forceinline__ void ld4(const double* p, bool ok, d4& v) {
+  if (VEC) {
+    const double2 x0 = ok ? *reinterpret_cast<const double2*>(p) : double2{0.0, 0.0};
+    const double2 x1 = ok ? *reinterpret_cast<const double2*>(p + 2) : double2{0.0, 0.0};
+    v[0] = x0.x; v[1] = x0.y; v[2] = x1.x; v[3] = x1.y;
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = ok ? p[r] : 0.0;
+  }
+}
+template <bool VEC>
+__device__ __forceinline__ void st4(double* p, const d4& v) {
+  if (VEC) {
+    *reinterpret_cast<double2*>(p) = double2{v[0], v[1]};
+    *reinterpret_cast<double2*>(p + 2) = double2{v[2], v[3]};
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) p[r] = v[r];
+  }
+}
+
 // column of a 16-column tile that result row x (= 4r + g) stands for
 __host__ __device__ constexpr int sig(int x) { return 4 * (x & 3) + (x >> 2); }
 
@@ -238,13 +272,98 @@ __global__ __launch_bounds__(PC_THREADS, 1) void k_pc_trsm(
   }
 }
 
+// The solve alone (no Gram), for callers that form Q^T Q with the staged Gram kernel: only
+// the operand tiles live in the local data share, so two workgroups share a CU, and each
+// wave solves two 16-row tiles whose dependent chains of matrix-core steps interleave.
+// Chunks of 128 rows (4 waves x 32) go to the workgroups in turn.  Same in-place rule as
+// k_pc_trsm.
+template <int NT, typename TA, bool VEC>
+__global__ __launch_bounds__(PC_THREADS, 2) void k_pc_trsm2(
+    const TA* X, int64_t ldx, int64_t m, int n, const double* __restrict__ Rop, double* Q,
+    int64_t ldq, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  constexpr int NTT = pc_pairs<NT>();
+  constexpr int CH = 2 * PC_CHUNK;
+  extern __shared__ double smem[];
+  double* Rs = smem;  // NTT * 256
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  for (int i = tid; i < NTT * 256; i += PC_THREADS) Rs[i] = Rop[i];
+  __syncthreads();
+  const int64_t nchunk = (m + CH - 1) / CH;
+  for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    // the operand tiles are read per use: without this compiler barrier all of them would
+    // be hoisted out of the loop into registers (and spilled)
+    asm volatile("" ::: "memory");
+    int64_t row[2];
+    bool rok[2];
+    const TA* xr[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      row[h] = ch * CH + 32 * wave + 16 * h + li;
+      rok[h] = row[h] < m;
+      xr[h] = X + (rok[h] ? row[h] : 0) * ldx;
+    }
+    d4 q[2][NT];
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+      d4 acc[2];
+      const int c0 = 16 * J + 4 * g;  // groups of four are whole: n % 4 == 0 when VEC
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (VEC) {
+          ld4<true>(xr[h] + c0, rok[h] && c0 < n, acc[h]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            acc[h][r] = (rok[h] && c0 + r < n) ? (double)xr[h][c0 + r] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int K = 0; K < J; ++K) {
+        const double* op = Rs + upk(K, J, NT) * 256 + lane;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double o = op[64 * s];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) acc[h] = mma(o, q[h][K][s], acc[h]);
+        }
+      }
+      const double* od = Rs + upk(J, J, NT) * 256 + lane;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) q[h][J] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double o = od[64 * s];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) q[h][J] = mma(o, acc[h][s], q[h][J]);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      double* qr = Q + (rok[h] ? row[h] : 0) * ldq;
+#pragma unroll
+      for (int J = 0; J < NT; ++J) {
+        const int c0 = 16 * J + 4 * g;
+        if (VEC) {
+          if (rok[h] && c0 < n) st4<true>(qr + c0, q[h][J]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (rok[h] && c0 + r < n) qr[c0 + r] = q[h][J][r];
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- row-local product
 // X <- X N in place (X: m x n float64, stride ldx; N: n x n).  A wave loads its 16 rows (lane
 // i: row i, four adjacent columns 4g .. 4g+3 of each tile as the A operand), forms each
 // output tile from all of them and stores it in result layout (row 4r + g, column i), so
 // every store depends on every load of the wave's rows.  Nop holds N as B operands: tile
 // (K, J), instruction s, lane (i, g): N[16K + 4g + s][16J + i].
-template <int NT>
+template <int NT, bool VEC>
 __global__ __launch_bounds__(PC_THREADS, 1) void k_rowmul(double* X, int64_t ldx, int64_t m,
                                                           int n,
                                                           const double* __restrict__ Nop,
@@ -261,14 +380,17 @@ __global__ __launch_bounds__(PC_THREADS, 1) void k_rowmul(double* X, int64_t ldx
     const int64_t rowa = r0 + li;
     const bool aok = rowa < m;
     const double* xa = X + (aok ? rowa : 0) * ldx;
-    double xv[NT][4];
+    d4 xv[NT];
 #pragma unroll
-    for (int K = 0; K < NT; ++K)
+    for (int K = 0; K < NT; ++K) {
+      const int c0 = 16 * K + 4 * g;
+      if (VEC) {
+        ld4<true>(xa + c0, aok && c0 < n, xv[K]);
+      } else {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int col = 16 * K + 4 * g + s;
-        xv[K][s] = (aok && col < n) ? xa[col] : 0.0;
+        for (int s = 0; s < 4; ++s) xv[K][s] = (aok && c0 + s < n) ? xa[c0 + s] : 0.0;
       }
+    }
 #pragma unroll
     for (int J = 0; J < NT; ++J) {
       d4 y = {0.0, 0.0, 0.0, 0.0};
@@ -375,8 +497,9 @@ size_t trsm_lds() {
 template <int NT>
 hipError_t pc_launch_nt(const double* R, int ldr, int n, double tol, double* Rp, double* Rop,
                         const void* Xv, int x_dtype, int64_t ldx, int64_t m, double* Q,
-                        int64_t ldq, double* part, int grid, const int* gate, hipStream_t s) {
+                        int64_t ldq, double* part, bool gram, const int* gate, hipStream_t s) {
   static bool attr = false;
+  const size_t lds2 = (size_t)pc_pairs<NT>() * 256 * sizeof(double);
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_pc_trsm<NT, float>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -385,6 +508,14 @@ hipError_t pc_launch_nt(const double* R, int ldr, int n, double tol, double* Rp,
     e = hipFuncSetAttribute((const void*)k_pc_trsm<NT, double>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)trsm_lds<NT>());
     if (e != hipSuccess) return e;
+    const void* k2[4] = {(const void*)k_pc_trsm2<NT, float, false>,
+                         (const void*)k_pc_trsm2<NT, float, true>,
+                         (const void*)k_pc_trsm2<NT, double, false>,
+                         (const void*)k_pc_trsm2<NT, double, true>};
+    for (const void* f : k2) {
+      e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
+      if (e != hipSuccess) return e;
+    }
     e = hipFuncSetAttribute((const void*)k_pc_prep<NT>,
                             hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(16 * NT * (16 * NT + 1) * sizeof(double)));
@@ -394,12 +525,39 @@ hipError_t pc_launch_nt(const double* R, int ldr, int n, double tol, double* Rp,
   hipLaunchKernelGGL(k_pc_prep<NT>, dim3(1), dim3(256),
                      (size_t)16 * NT * (16 * NT + 1) * sizeof(double), s, R, ldr, n, tol, Rp,
                      Rop);
-  if (x_dtype == TSSVD_F32)
-    hipLaunchKernelGGL((k_pc_trsm<NT, float>), dim3(grid), dim3(PC_THREADS), trsm_lds<NT>(), s,
-                       (const float*)Xv, ldx, m, n, Rop, Q, ldq, part, gate);
-  else
-    hipLaunchKernelGGL((k_pc_trsm<NT, double>), dim3(grid), dim3(PC_THREADS), trsm_lds<NT>(),
-                       s, (const double*)Xv, ldx, m, n, Rop, Q, ldq, part, gate);
+  if (gram) {
+    const int grid = pc_grid(m);
+    if (x_dtype == TSSVD_F32)
+      hipLaunchKernelGGL((k_pc_trsm<NT, float>), dim3(grid), dim3(PC_THREADS), trsm_lds<NT>(),
+                         s, (const float*)Xv, ldx, m, n, Rop, Q, ldq, part, gate);
+    else
+      hipLaunchKernelGGL((k_pc_trsm<NT, double>), dim3(grid), dim3(PC_THREADS),
+                         trsm_lds<NT>(), s, (const double*)Xv, ldx, m, n, Rop, Q, ldq, part,
+                         gate);
+  } else {
+    const int64_t nch = (m + 2 * PC_CHUNK - 1) / (2 * PC_CHUNK);
+    const int grid = (int)(nch < 2 * PC_GRID_MAX ? (nch > 0 ? nch : 1) : 2 * PC_GRID_MAX);
+    // vector accesses when every row of X and Q starts on 16 bytes and n is whole fours
+    const size_t xs = x_dtype == TSSVD_F32 ? 4 : 8;
+    const bool vec = n % 4 == 0 && (reinterpret_cast<uintptr_t>(Xv) & 15) == 0 &&
+                     (ldx * xs) % 16 == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0 &&
+                     (ldq * 8) % 16 == 0;
+    if (x_dtype == TSSVD_F32) {
+      if (vec)
+        hipLaunchKernelGGL((k_pc_trsm2<NT, float, true>), dim3(grid), dim3(PC_THREADS), lds2,
+                           s, (const float*)Xv, ldx, m, n, Rop, Q, ldq, gate);
+      else
+        hipLaunchKernelGGL((k_pc_trsm2<NT, float, false>), dim3(grid), dim3(PC_THREADS), lds2,
+                           s, (const float*)Xv, ldx, m, n, Rop, Q, ldq, gate);
+    } else {
+      if (vec)
+        hipLaunchKernelGGL((k_pc_trsm2<NT, double, true>), dim3(grid), dim3(PC_THREADS), lds2,
+                           s, (const double*)Xv, ldx, m, n, Rop, Q, ldq, gate);
+      else
+        hipLaunchKernelGGL((k_pc_trsm2<NT, double, false>), dim3(grid), dim3(PC_THREADS), lds2,
+                           s, (const double*)Xv, ldx, m, n, Rop, Q, ldq, gate);
+    }
+  }
   return hipGetLastError();
 }
 
@@ -409,15 +567,24 @@ hipError_t rowmul_nt(double* X, int64_t ldx, int64_t m, int n, const double* N, 
   static bool attr = false;
   const size_t lds = (size_t)NT * NT * 256 * sizeof(double);
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_rowmul<NT>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_rowmul<NT, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)k_rowmul<NT, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr = true;
   }
   hipLaunchKernelGGL(k_pack_rowmul<NT>, dim3((NT * NT * 256 + 255) / 256), dim3(256), 0, s, N,
                      ldn, n, Nop);
-  hipLaunchKernelGGL(k_rowmul<NT>, dim3(grid), dim3(PC_THREADS), lds, s, X, ldx, m, n, Nop,
-                     gate);
+  // vector loads when every row of X starts on 16 bytes and n is whole fours
+  const bool vec = n % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0 && ldx % 2 == 0;
+  if (vec)
+    hipLaunchKernelGGL((k_rowmul<NT, true>), dim3(grid), dim3(PC_THREADS), lds, s, X, ldx, m,
+                       n, Nop, gate);
+  else
+    hipLaunchKernelGGL((k_rowmul<NT, false>), dim3(grid), dim3(PC_THREADS), lds, s, X, ldx, m,
+                       n, Nop, gate);
   return hipGetLastError();
 }
 
@@ -436,19 +603,19 @@ size_t pc_op_elems(int n) {
 
 hipError_t pc_trsm_gram(const double* R, int ldr, int n, double tol, double* Rp, double* Rop,
                         const void* X, int x_dtype, int64_t ldx, int64_t m, double* Q,
-                        int64_t ldq, double* part, double* G, const int* gate, hipStream_t s) {
-  const int grid = pc_grid(m);
+                        int64_t ldq, double* part, double* G, const int* gate, hipStream_t s,
+                        bool gram) {
   hipError_t e;
   switch ((n + 15) / 16) {
-    case 3: e = pc_launch_nt<3>(R, ldr, n, tol, Rp, Rop, X, x_dtype, ldx, m, Q, ldq, part, grid, gate, s); break;
-    case 4: e = pc_launch_nt<4>(R, ldr, n, tol, Rp, Rop, X, x_dtype, ldx, m, Q, ldq, part, grid, gate, s); break;
-    case 5: e = pc_launch_nt<5>(R, ldr, n, tol, Rp, Rop, X, x_dtype, ldx, m, Q, ldq, part, grid, gate, s); break;
-    case 6: e = pc_launch_nt<6>(R, ldr, n, tol, Rp, Rop, X, x_dtype, ldx, m, Q, ldq, part, grid, gate, s); break;
-    case 7: e = pc_launch_nt<7>(R, ldr, n, tol, Rp, Rop, X, x_dtype, ldx, m, Q, ldq, part, grid, gate, s); break;
+    case 3: e = pc_launch_nt<3>(R, ldr, n, tol, Rp, Rop, X, x_dtype, ldx, m, Q, ldq, part, gram, gate, s); break;
+    case 4: e = pc_launch_nt<4>(R, ldr, n, tol, Rp, Rop, X, x_dtype, ldx, m, Q, ldq, part, gram, gate, s); break;
+    case 5: e = pc_launch_nt<5>(R, ldr, n, tol, Rp, Rop, X, x_dtype, ldx, m, Q, ldq, part, gram, gate, s); break;
+    case 6: e = pc_launch_nt<6>(R, ldr, n, tol, Rp, Rop, X, x_dtype, ldx, m, Q, ldq, part, gram, gate, s); break;
+    case 7: e = pc_launch_nt<7>(R, ldr, n, tol, Rp, Rop, X, x_dtype, ldx, m, Q, ldq, part, gram, gate, s); break;
     default: return hipErrorInvalidValue;
   }
-  if (e != hipSuccess) return e;
-  return reduce_chunks(part, grid, n, n, G, n, s);
+  if (e != hipSuccess || !gram) return e;
+  return reduce_chunks(part, pc_grid(m), n, n, G, n, s);
 }
 
 hipError_t pc_rowmul(double* X, int64_t ldx, int64_t m, int n, const double* N, int ldn,

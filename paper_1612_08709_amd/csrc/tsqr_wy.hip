@@ -193,6 +193,17 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
+// Four adjacent elements from a 16-byte aligned address, as vector loads.
+__device__ __forceinline__ void load4_aligned(const double* p, double (&v)[4]) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void load4_aligned(const float* p, float (&v)[4]) {
+  const float4 a = *reinterpret_cast<const float4*>(p);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+
 // Index of the upper tile (p, c), p <= c, in the packed tile list of an NT x NT grid.
 __host__ __device__ constexpr int utile(int p, int c, int nt) { return p * nt - p * (p - 1) / 2 + (c - p); }
 // Index of the strictly upper pair (c, q), c < q.
@@ -556,11 +567,17 @@ __global__ __launch_bounds__(64 * WA_WAVES) void k_wy_apply(
     // this wave's rows of V (phase 2), as A operands: row 16 wave + i, 16-column group q
     CT va[NT][4];
     {
+      // rows of V are 16-byte aligned (the workspace is, and a row is 16 NT elements)
       const CT* vr = Vb + (int64_t)(16 * wave + li) * LDV + 4 * g;
 #pragma unroll
-      for (int q = 0; q < NT; ++q)
+      for (int q = 0; q < NT; ++q) {
+        if (q < np) {
+          load4_aligned(vr + 16 * q, va[q]);
+        } else {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) va[q][t] = (q < np) ? vr[16 * q + t] : zero;
+          for (int t = 0; t < 4; ++t) va[q][t] = zero;
+        }
+      }
     }
     // ---- phase 1: W = T S, last panel first
     if (cwave) {

@@ -221,6 +221,22 @@ def test_sketch_and_cotangent_checks_reject_misread_layouts(native):
         T._check_cotangent(torch.zeros(7, 4), (7, 3), "gU", "cpu")
 
 
+def test_misaligned_workspace_is_rejected_on_the_host(native):
+    """The workspace must start on 256 bytes; a misaligned one is refused before anything is
+    enqueued (fake device pointers: no kernel may run)."""
+    lib, N = native.lib(), native
+    o = N.default_opts()
+    fake = C.c_void_p(0x1000)
+    nb = C.c_size_t()
+    assert lib.tssvd_workspace_bytes(1000, 10, N.F64, C.byref(o), C.byref(nb)) == N.OK
+    st = lib.tssvd(fake, N.F64, 1000, 10, 10, fake, 10, fake, fake, 10, None,
+                   C.c_void_p(0x1010), nb.value + 256, C.byref(o), None)
+    assert st == N.E_WORKSPACE
+    assert lib.tsqr_workspace_bytes(1000, 10, N.F64, C.byref(nb)) == N.OK
+    assert lib.tsqr(fake, N.F64, 1000, 10, 10, fake, 10, fake, 10, C.c_void_p(0x1080),
+                    nb.value + 256, None) == N.E_WORKSPACE
+
+
 def test_noalloc_rejects_before_touching_the_device(native):
     """tssvd_noalloc checks its arguments and the scratch limit on the host first."""
     lib, N = native.lib(), native
