@@ -162,9 +162,11 @@ hipError_t gemm_atq_mixed(const float* A, int64_t lda, int64_t m, int64_t n, con
 // gate, the solve runs only if *gate != 0 (the preparation and the reduction always run).
 int pc_grid(int64_t m);
 size_t pc_op_elems(int n);
+// gram = false: the solve only (Q written, G and part untouched).
 hipError_t pc_trsm_gram(const double* R, int ldr, int n, double tol, double* Rp, double* Rop,
                         const void* X, int x_dtype, int64_t ldx, int64_t m, double* Q,
-                        int64_t ldq, double* part, double* G, const int* gate, hipStream_t s);
+                        int64_t ldq, double* part, double* G, const int* gate, hipStream_t s,
+                        bool gram = true);
 // X <- X N in place (X m x n float64, stride ldx; N n x n, stride ldn); Nop: pc_op_elems(n).
 hipError_t pc_rowmul(double* X, int64_t ldx, int64_t m, int n, const double* N, int ldn,
                      double* Nop, const int* gate, hipStream_t s);
