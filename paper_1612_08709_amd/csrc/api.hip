@@ -125,11 +125,14 @@ __global__ __launch_bounds__(256) void k_ortho_gate(const double* __restrict__ G
 // angle between column k of Y and the span of the earlier columns) drops direction k: row k
 // of R stays zero and there is no trailing update, so Y = Q R still holds with the dropped
 // column's coefficients in column k of R, and Q has no column k; dead[k] = 1 marks it.
+// With `gate` given and *gate == 0 the kernel does nothing (a step that is not taken).
 __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ G, int l,
                                               double* __restrict__ R, int* __restrict__ bad,
-                                              double dead_tol, int* __restrict__ dead) {
+                                              double dead_tol, int* __restrict__ dead,
+                                              const int* __restrict__ gate) {
   extern __shared__ double Gs[];  // l x l, row-major
   __shared__ unsigned char sdead[TSSVD_N_MAX];
+  if (gate && *gate == 0) return;  // uniform over the workgroup
   const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
   for (int i = tid; i < l * l; i += 256) {
     Gs[i] = G[i];
@@ -166,7 +169,8 @@ __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ G, int 
 // Rm = R with each dropped direction's column replaced by e_k (row k of R is zero): the
 // nonsingular matrix whose inverse, with row k zeroed, maps Y to the kept basis.
 __global__ void k_unit_dead(const double* __restrict__ R, const int* __restrict__ dead, int l,
-                            double* __restrict__ Rm) {
+                            double* __restrict__ Rm, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= l * l) return;
   const int i = idx / l, j = idx - i * l;
@@ -179,7 +183,8 @@ __global__ void k_unit_dead(const double* __restrict__ R, const int* __restrict_
 // need not be formed by the reverse Householder pass.  Rounding in Y R^-1 grows with
 // kappa(R); when the Frobenius estimate ||R||_F ||R^-1||_F exceeds kappa_max (or R^-1 is
 // not finite, e.g. for a rank-deficient sketch) the kernel sets *use_q = 1 and T = I, and
-// the gated Householder apply forms Q explicitly.
+// the gated Householder apply forms Q explicitly.  With `gate` given and *gate == 0 the
+// kernel does nothing.
 // 1024 threads: the 16-lane group c (c += 64) solves R t = e_c bottom-up with no barrier;
 // lane L keeps t_k for k = L (mod 16) in registers and the dot products are 16-lane sums.
 constexpr int RINV_THREADS = 1024;
@@ -189,10 +194,12 @@ __global__ __launch_bounds__(RINV_THREADS) void k_rinv_gate(const double* __rest
                                                             double kappa_max,
                                                             double* __restrict__ T,
                                                             int* __restrict__ use_q,
-                                                            const int* __restrict__ force) {
+                                                            const int* __restrict__ force,
+                                                            const int* __restrict__ gate) {
   extern __shared__ double Rs[];  // l x l, row-major
   __shared__ double red[2][RINV_THREADS / 16];
   __shared__ int bad;
+  if (gate && *gate == 0) return;  // uniform over the workgroup
   const int tid = threadIdx.x, L = tid & 15, grp = tid >> 4;
   for (int i = tid; i < l * l; i += RINV_THREADS) Rs[i] = R[i];
   __syncthreads();
@@ -705,20 +712,22 @@ hipError_t tssvd_mixed(const void* A, int64_t m, int ni, int64_t lda, double* U,
   MTRY(chol_rinv_attrs());
   const size_t lds = (size_t)ni * ni * sizeof(double);
   hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), lds, s, w.G, ni, w.Rc, w.mflags,
-                     kMixedDeadSine2, w.mdead);                         // R2 (kept columns)
-  hipLaunchKernelGGL(k_unit_dead, dim3(nb), dim3(256), 0, s, w.Rc, w.mdead, ni, w.Rcm);
+                     kMixedDeadSine2, w.mdead, (const int*)nullptr);  // R2 (kept columns)
+  hipLaunchKernelGGL(k_unit_dead, dim3(nb), dim3(256), 0, s, w.Rc, w.mdead, ni, w.Rcm,
+                     (const int*)nullptr);
   hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), lds, s, w.Rcm, ni, 1e300, w.Ri,
-                     w.mflags + 1, (const int*)nullptr);
+                     w.mflags + 1, (const int*)nullptr, (const int*)nullptr);
   MTRY(pc_kappa_flag(w.G, w.Ri, ni, kPcKappa, w.mflags + 2, s));
-  // second pass Q2 = Q1 R2m^-1, gated on mflags[2] (its preparation, reduction and small
-  // steps always run)
+  // second pass Q2 = Q1 R2m^-1 with its Cholesky and inverse, every step gated on mflags[2]
+  // (k_pc_combine reads none of their outputs when the flag is 0)
+  const int* g2 = w.mflags + 2;
   MTRY(pc_trsm_gram(w.Rcm, ni, ni, kPcClamp, w.Rp2, w.op, U, TSSVD_F64, ldu, m, U, ldu,
-                    w.pcpart, w.G2, w.mflags + 2, s));
+                    w.pcpart, w.G2, g2, s));
   hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), lds, s, w.G2, ni, w.R3, w.mflags + 3,
-                     kMixedDeadSine2, w.mdead2);
-  hipLaunchKernelGGL(k_unit_dead, dim3(nb), dim3(256), 0, s, w.R3, w.mdead2, ni, w.R3m);
+                     kMixedDeadSine2, w.mdead2, g2);
+  hipLaunchKernelGGL(k_unit_dead, dim3(nb), dim3(256), 0, s, w.R3, w.mdead2, ni, w.R3m, g2);
   hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), lds, s, w.R3m, ni, 1e300, w.R3i,
-                     w.mflags + 1, (const int*)nullptr);
+                     w.mflags + 1, (const int*)nullptr, g2);
   MTRY(pc_combine(w.mflags, w.Rp, w.Rc, w.Rp2, w.Ri, w.R3, w.R3i, w.mdead, w.mdead2, ni,
                   w.Rtot, w.Ninv, info, s));
   MTRY(jacobi_svd(w.Rtot, ni, ni, 1, 0.0, o.max_jacobi_sweeps, 1, w.Vt, w.S, w.Ut, info, s));
@@ -1099,9 +1108,9 @@ hipError_t basis_via_r(const TsqrPlan& p, double* Y, int64_t rows, int l, const 
                        chol_bad);
   } else {
     hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), (size_t)l * l * sizeof(double), s, G, l, Rc,
-                       chol_bad, 0.0, (int*)nullptr);
+                       chol_bad, 0.0, (int*)nullptr, (const int*)nullptr);
     hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), (size_t)l * l * sizeof(double),
-                       s, Rc, l, kmax, T, use_q, chol_bad);
+                       s, Rc, l, kmax, T, use_q, chol_bad, (const int*)nullptr);
   }
   TsqrPlan pq = p;
   pq.gate = use_q;

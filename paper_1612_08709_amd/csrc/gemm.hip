@@ -302,7 +302,8 @@ __global__ __launch_bounds__(256) void k_gemm_atq_f64(const TA* __restrict__ A, 
 
 __global__ void k_reduce_chunks_strided(const double* __restrict__ part, int nchunk,
                                         int64_t count, int64_t stride, double* __restrict__ Z,
-                                        int l, int ldz) {
+                                        int l, int ldz, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= count) return;
   double s = 0.0;
@@ -313,7 +314,9 @@ __global__ void k_reduce_chunks_strided(const double* __restrict__ part, int nch
 }
 
 __global__ void k_reduce_chunks(const double* __restrict__ part, int nchunk, int64_t count,
-                                double* __restrict__ Z, int l, int ldz) {
+                                double* __restrict__ Z, int l, int ldz,
+                                const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= count) return;
   // chunk order is fixed (bitwise reproducible); the loads of eight chunks are issued
@@ -811,7 +814,9 @@ hipError_t gemm_atq_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int6
 
 // First level for many chunks: group gi adds chunks gi*G .. gi*G + G - 1 (in order) and
 // stores the sum over chunk gi*G's slot, which only this group reads.
-__global__ void k_reduce_groups(double* __restrict__ part, int nchunk, int64_t count, int G) {
+__global__ void k_reduce_groups(double* __restrict__ part, int nchunk, int64_t count, int G,
+                                const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= count) return;
   const int c0 = blockIdx.y * G;
@@ -830,7 +835,7 @@ __global__ void k_reduce_groups(double* __restrict__ part, int nchunk, int64_t c
 }
 
 hipError_t reduce_chunks(const double* part, int nchunk, int64_t n, int l, double* Z, int ldz,
-                         hipStream_t s) {
+                         hipStream_t s, const int* gate) {
   const int64_t count = n * (int64_t)l;
   if (nchunk > 64 && count < (1 << 16)) {
     // few outputs, many chunks (Grams of tall matrices): two fixed-order levels, so the
@@ -838,13 +843,13 @@ hipError_t reduce_chunks(const double* part, int nchunk, int64_t n, int l, doubl
     const int G = (nchunk + 63) / 64;
     const int ng = (nchunk + G - 1) / G;
     hipLaunchKernelGGL(k_reduce_groups, dim3((unsigned)((count + 255) / 256), ng), dim3(256), 0,
-                       s, const_cast<double*>(part), nchunk, count, G);
+                       s, const_cast<double*>(part), nchunk, count, G, gate);
     hipLaunchKernelGGL(k_reduce_chunks_strided, dim3((unsigned)((count + 255) / 256)),
-                       dim3(256), 0, s, part, ng, count, (int64_t)G * count, Z, l, ldz);
+                       dim3(256), 0, s, part, ng, count, (int64_t)G * count, Z, l, ldz, gate);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
-                     part, nchunk, count, Z, l, ldz);
+                     part, nchunk, count, Z, l, ldz, gate);
   return hipGetLastError();
 }
 

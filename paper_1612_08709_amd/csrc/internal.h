@@ -120,7 +120,7 @@ size_t lu_index_ints(int64_t rows, int l);
 hipError_t lu_tracking_T(const double* Y, int64_t rows, int l, int64_t ldy, int* idx, double* T,
                          int* use_q, hipStream_t s);
 hipError_t reduce_chunks(const double* part, int nchunk, int64_t n, int l, double* Z, int ldz,
-                         hipStream_t s);
+                         hipStream_t s, const int* gate = nullptr);
 
 // Mixed precision (A stored float32).  kind: operand packing / MFMA flavour.
 constexpr int MIX_BF16 = 0;    // bfloat16 inputs, float32 accumulation
@@ -159,7 +159,7 @@ hipError_t gemm_atq_mixed(const float* A, int64_t lda, int64_t m, int64_t n, con
 // Rp = R with diagonal entries below tol max|R_ii| raised to that size; Q = X Rp^-1 (X m x n
 // float32 or float64, stride ldx; Q float64, stride ldq, may be X itself for float64) and
 // G = Q^T Q (n x n).  Rop: pc_op_elems(n) doubles; part: pc_grid(m) n n doubles.  With a
-// gate, the solve runs only if *gate != 0 (the preparation and the reduction always run).
+// gate, every kernel (preparation, solve, reduction) does its work only if *gate != 0.
 int pc_grid(int64_t m);
 size_t pc_op_elems(int n);
 // gram = false: the solve only (Q written, G and part untouched).

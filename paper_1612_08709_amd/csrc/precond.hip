@@ -106,10 +106,12 @@ constexpr int stage_ld() { return 16 * NT + 2; }  // staging row stride (doubles
 template <int NT>
 __global__ __launch_bounds__(256) void k_pc_prep(const double* __restrict__ R, int ldr, int n,
                                                  double tol, double* __restrict__ Rp,
-                                                 double* __restrict__ Rop) {
+                                                 double* __restrict__ Rop,
+                                                 const int* __restrict__ gate) {
   constexpr int NP = 16 * NT, LD = NP + 1;
   extern __shared__ double Rl[];  // NP x LD: the padded factor, then the block inverses
   __shared__ double s_thr;
+  if (gate && *gate == 0) return;  // uniform over the workgroup
   const int tid = threadIdx.x;
   for (int idx = tid; idx < NP * NP; idx += 256) {
     const int i = idx / NP, j = idx - i * NP;
@@ -524,7 +526,7 @@ hipError_t pc_launch_nt(const double* R, int ldr, int n, double tol, double* Rp,
   }
   hipLaunchKernelGGL(k_pc_prep<NT>, dim3(1), dim3(256),
                      (size_t)16 * NT * (16 * NT + 1) * sizeof(double), s, R, ldr, n, tol, Rp,
-                     Rop);
+                     Rop, gate);
   if (gram) {
     const int grid = pc_grid(m);
     if (x_dtype == TSSVD_F32)
@@ -615,7 +617,7 @@ hipError_t pc_trsm_gram(const double* R, int ldr, int n, double tol, double* Rp,
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess || !gram) return e;
-  return reduce_chunks(part, pc_grid(m), n, n, G, n, s);
+  return reduce_chunks(part, pc_grid(m), n, n, G, n, s, gate);
 }
 
 hipError_t pc_rowmul(double* X, int64_t ldx, int64_t m, int n, const double* N, int ldn,
