@@ -63,7 +63,43 @@ __device__ __forceinline__ void load4(const float* p, bool full, int valid, doub
 // each entry rounded once from its float64 value, exactly what packing the stored Y gives.
 // The MFMA result rows 16 rt + 4 r + g of a lane become the fragment rows 8 g + e through
 // a bfloat16 transpose in LDS.
-template <int RT, int NT, typename TA, bool PACK = false>
+//
+// VEC (every row of A starts on 16 bytes and n is a multiple of 4): the main loop has no
+// branch and no masked load, so the loads of the next step stay in flight while this
+// step's MFMAs run (a load under a lane condition makes the compiler wait for it at the
+// end of its branch).  Rows past m read row m - 1 and columns past l of X read column
+// l - 1: those results are never stored.  The steps alternate between two register sets;
+// a last step of fewer than 16 columns (n % 16 = 4, 8 or 12) is done once with a lane
+// condition.
+// Four consecutive entries of a row of A as one register quad: a 16-byte load for float32,
+// two for float64.  pin() is an empty asm statement that reads and writes the quad, so the
+// float32 -> float64 conversions of one pipeline slot cannot be scheduled above it (they
+// would make the wave wait for the loads of the later slots).
+template <typename TA>
+struct Quad;
+template <>
+struct Quad<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  v4 v;
+  __device__ __forceinline__ void load(const float* p) { v = *reinterpret_cast<const v4*>(p); }
+  __device__ __forceinline__ void zero() { v = v4{0.f, 0.f, 0.f, 0.f}; }
+  __device__ __forceinline__ void pin() { asm volatile("" : "+v"(v)); }
+  __device__ __forceinline__ double operator[](int s) const { return (double)v[s]; }
+};
+template <>
+struct Quad<double> {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  v2 lo, hi;
+  __device__ __forceinline__ void load(const double* p) {
+    lo = *reinterpret_cast<const v2*>(p);
+    hi = *reinterpret_cast<const v2*>(p + 2);
+  }
+  __device__ __forceinline__ void zero() { lo = hi = v2{0.0, 0.0}; }
+  __device__ __forceinline__ void pin() { asm volatile("" : "+v"(lo), "+v"(hi)); }
+  __device__ __forceinline__ double operator[](int s) const { return s < 2 ? lo[s] : hi[s - 2]; }
+};
+
+template <int RT, int NT, typename TA, bool PACK = false, bool VEC = false>
 __global__ __launch_bounds__(256) void k_gemm_ax_f64(const TA* __restrict__ A, int64_t lda,
                                                      int64_t m, int n,
                                                      const double* __restrict__ X, int ldx,
@@ -77,54 +113,126 @@ __global__ __launch_bounds__(256) void k_gemm_ax_f64(const TA* __restrict__ A, i
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const TA* arow[RT];
-  bool rok[RT];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    const int64_t row = rbase + 16 * rt + li;
-    rok[rt] = row < m;
-    arow[rt] = A + (rok[rt] ? row : 0) * lda;
-  }
-  auto load_a = [&](int k0, double (&a)[RT][4]) {
-    const int kb = k0 + 4 * g;
-    const int valid = n - kb;
+  if constexpr (VEC) {
+    const TA* ar[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-      if (rok[rt] && valid > 0) {
-        load4(arow[rt] + kb, valid >= 4, valid, a[rt]);
-      } else {
+      const int64_t row = rbase + 16 * rt + li;
+      ar[rt] = A + (row < m ? row : m - 1) * lda + 4 * g;
+    }
+    int xc[NT];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) a[rt][s] = 0.0;
+    for (int nt = 0; nt < NT; ++nt) xc[nt] = (16 * nt + li < l) ? 16 * nt + li : l - 1;
+    const double* xg = X + (int64_t)(4 * g) * ldx;
+    auto ld = [&](int k0, Quad<TA> (&a)[RT], double (&x)[NT][4]) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) a[rt].load(ar[rt] + k0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) x[nt][s] = xg[(int64_t)(k0 + s) * ldx + xc[nt]];
+    };
+    auto mm = [&](Quad<TA> (&a)[RT], const double (&x)[NT][4]) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) a[rt].pin();
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mfma_f64(a[rt][s], x[nt][s], acc[rt][nt]);
+    };
+    const int nfull = n >> 4;  // whole 16-column steps
+    Quad<TA> a0[RT], a1[RT];
+    double x0[NT][4], x1[NT][4];
+    int st = 0;
+    if (nfull & 1) {
+      ld(0, a0, x0);
+      mm(a0, x0);
+      st = 1;
+    }
+    if (st < nfull) {  // an even number of steps remains
+      ld(16 * st, a0, x0);
+      for (; st < nfull; st += 2) {
+        // the empty asm statements keep each step's loads ahead of the other step's MFMAs
+        // (without them the compiler moves the loads down to their uses)
+        ld(16 * (st + 1), a1, x1);
+        asm volatile("" ::: "memory");
+        mm(a0, x0);
+        ld(16 * (st + 2 < nfull ? st + 2 : st + 1), a0, x0);  // the last one is not used
+        asm volatile("" ::: "memory");
+        mm(a1, x1);
       }
     }
-  };
-  double a[RT][4];
-  load_a(0, a);
-  for (int k0 = 0; k0 < n; k0 += 16) {
-    double an[RT][4], x[NT][4];
-    const int kn = (k0 + 16 < n) ? k0 + 16 : k0;
-    load_a(kn, an);
-    const int kb = k0 + 4 * g;
+    if (16 * nfull < n) {
+      const int kb = 16 * nfull + 4 * g;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int kk = kb + s;
-      const bool kok = kk < n;
+      for (int rt = 0; rt < RT; ++rt) a0[rt].zero();
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int col = 16 * nt + li;
-        x[nt][s] = (kok && col < l) ? X[(int64_t)kk * ldx + col] : 0.0;
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) x0[nt][s] = 0.0;
+      if (kb < n) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) a0[rt].load(ar[rt] + 16 * nfull);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            x0[nt][s] = xg[(int64_t)(16 * nfull + s) * ldx + xc[nt]];
       }
+      mm(a0, x0);
     }
+  } else {
+    const TA* arow[RT];
+    bool rok[RT];
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int rt = 0; rt < RT; ++rt) {
+      const int64_t row = rbase + 16 * rt + li;
+      rok[rt] = row < m;
+      arow[rt] = A + (rok[rt] ? row : 0) * lda;
+    }
+    auto load_a = [&](int k0, double (&a)[RT][4]) {
+      const int kb = k0 + 4 * g;
+      const int valid = n - kb;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        if (rok[rt] && valid > 0) {
+          load4(arow[rt] + kb, valid >= 4, valid, a[rt]);
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) a[rt][s] = 0.0;
+        }
+      }
+    };
+    double a[RT][4];
+    load_a(0, a);
+    for (int k0 = 0; k0 < n; k0 += 16) {
+      double an[RT][4], x[NT][4];
+      const int kn = (k0 + 16 < n) ? k0 + 16 : k0;
+      load_a(kn, an);
+      const int kb = k0 + 4 * g;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kk = kb + s;
+        const bool kok = kk < n;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int col = 16 * nt + li;
+          x[nt][s] = (kok && col < l) ? X[(int64_t)kk * ldx + col] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mfma_f64(a[rt][s], x[nt][s], acc[rt][nt]);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mfma_f64(a[rt][s], x[nt][s], acc[rt][nt]);
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) a[rt][s] = an[rt][s];
+        for (int s = 0; s < 4; ++s) a[rt][s] = an[rt][s];
+    }
   }
   if constexpr (PACK) {
     static_assert(RT == 2, "one 32-row block per wave");
@@ -158,13 +266,26 @@ __global__ __launch_bounds__(256) void k_gemm_ax_f64(const TA* __restrict__ A, i
     }
 }
 
+// The branch-free main loop of k_gemm_ax_f64 applies when every row of A starts on 16 bytes
+// and the contraction length is a multiple of 4.
+template <typename TA>
+static bool ax_vec(const TA* A, int64_t lda, int64_t n) {
+  return (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (lda * (int64_t)sizeof(TA)) % 16 == 0 &&
+         n % 4 == 0;
+}
+
 template <int NT>
 static void launch_ax_pack(const double* Y, int64_t ldy, int64_t m, const double* T, int ldt,
                            int l, void* P, hipStream_t s) {
   constexpr int RT = 2;
   const int64_t grid = (m + 64 * RT - 1) / (64 * RT);
-  hipLaunchKernelGGL((k_gemm_ax_f64<RT, NT, double, true>), dim3((unsigned)grid), dim3(256), 0,
-                     s, Y, ldy, m, l, T, ldt, l, (double*)nullptr, 0, (bf16x8_t*)P);
+  if (ax_vec(Y, ldy, l))
+    hipLaunchKernelGGL((k_gemm_ax_f64<RT, NT, double, true, true>), dim3((unsigned)grid),
+                       dim3(256), 0, s, Y, ldy, m, l, T, ldt, l, (double*)nullptr, 0,
+                       (bf16x8_t*)P);
+  else
+    hipLaunchKernelGGL((k_gemm_ax_f64<RT, NT, double, true>), dim3((unsigned)grid), dim3(256),
+                       0, s, Y, ldy, m, l, T, ldt, l, (double*)nullptr, 0, (bf16x8_t*)P);
 }
 
 hipError_t gemm_ax_f64_pack_bf16(const double* Y, int64_t ldy, int64_t m, const double* T,
@@ -187,8 +308,12 @@ static void launch_ax(const TA* A, int64_t lda, int64_t m, int64_t n, const doub
                       int ldx, int l, double* Y, int ldy, hipStream_t s) {
   constexpr int RT = 2;
   const int64_t grid = (m + 64 * RT - 1) / (64 * RT);
-  hipLaunchKernelGGL((k_gemm_ax_f64<RT, NT, TA>), dim3((unsigned)grid), dim3(256), 0, s, A,
-                     lda, m, (int)n, X, ldx, l, Y, ldy);
+  if (ax_vec(A, lda, n))
+    hipLaunchKernelGGL((k_gemm_ax_f64<RT, NT, TA, false, true>), dim3((unsigned)grid),
+                       dim3(256), 0, s, A, lda, m, (int)n, X, ldx, l, Y, ldy, nullptr);
+  else
+    hipLaunchKernelGGL((k_gemm_ax_f64<RT, NT, TA>), dim3((unsigned)grid), dim3(256), 0, s, A,
+                       lda, m, (int)n, X, ldx, l, Y, ldy, nullptr);
 }
 
 template <typename TA>
@@ -226,7 +351,14 @@ hipError_t gemm_ax_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int64
 // The contraction runs over rows: in one MFMA, k-slot g is row r + g.
 constexpr int ATQ_COLS = 256;
 
-template <int NT, typename TA, bool RS, typename TQ = double>
+// VEC (every row of A starts on 16 bytes and n is a multiple of 4): the whole four-row
+// groups of the chunk run through a ring of ATQ_DEPTH groups in flight with no branch and
+// no masked load (as in k_gemm_ax_f64); columns past n read columns n - 4 .. n - 1 and
+// columns past l of Q read column l - 1, and those results are never stored.  The last
+// partial group is done once with a lane condition.
+constexpr int ATQ_DEPTH = 4;
+
+template <int NT, typename TA, bool RS, typename TQ = double, bool VEC = false>
 __global__ __launch_bounds__(256) void k_gemm_atq_f64(const TA* __restrict__ A, int64_t lda,
                                                       int64_t m, int n,
                                                       const TQ* __restrict__ Q, int ldq,
@@ -254,36 +386,90 @@ __global__ __launch_bounds__(256) void k_gemm_atq_f64(const TA* __restrict__ A, 
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f64x4{0.0, 0.0, 0.0, 0.0};
   const int cb = cw + 4 * li;
-  const int cvalid = n - cb;
-  auto load = [&](int64_t rq, double (&a)[4], double (&q)[NT]) {
-    const int64_t row = rq + g;
-    const bool rok = row < r1;
-    const int64_t rr = rok ? row : r0;
-    if (rok && cvalid > 0) {
-      load4(A + rr * lda + cb, cvalid >= 4, cvalid, a);
-    } else {
+  if constexpr (VEC) {
+    const TA* ap = A + (r0 + g) * lda + (cb < n ? cb : n - 4);
+    int qc[NT];
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt) a[mt] = 0.0;
+    for (int nt = 0; nt < NT; ++nt) qc[nt] = (16 * nt + li < l) ? 16 * nt + li : l - 1;
+    const TQ* qp = Q + (r0 + g) * ldq;
+    auto ld = [&](int64_t grp, Quad<TA>& a, double (&q)[NT]) {
+      a.load(ap + 4 * grp * lda);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) q[nt] = (double)qp[4 * grp * ldq + qc[nt]];
+    };
+    auto mm = [&](Quad<TA>& a, const double (&q)[NT]) {
+      a.pin();
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_f64(a[mt], q[nt], acc[mt][nt]);
+    };
+    const int64_t nfull = (r1 - r0) >> 2;                 // whole four-row groups
+    const int64_t nring = nfull / ATQ_DEPTH * ATQ_DEPTH;  // those run through the ring
+    Quad<TA> a[ATQ_DEPTH];
+    double q[ATQ_DEPTH][NT];
+    // first the groups after the ring: at most ATQ_DEPTH, the last possibly partial; rows
+    // past the chunk give zeros.  (Straight-line code before the loop: with MFMAs after
+    // the loop the compiler copies the accumulators in and out of it on every iteration.)
+#pragma unroll
+    for (int t = 0; t < ATQ_DEPTH; ++t) {
+      const int64_t gi = nring + t;
+      a[t].zero();
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) q[t][nt] = 0.0;
+      if (r0 + 4 * gi + g < r1) ld(gi, a[t], q[t]);
+      mm(a[t], q[t]);
     }
+    if (nring > 0) {
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int col = 16 * nt + li;
-      q[nt] = (rok && col < l) ? (double)Q[rr * ldq + col] : 0.0;
+      for (int d = 0; d < ATQ_DEPTH; ++d) {
+        ld(d, a[d], q[d]);
+        asm volatile("" ::: "memory");  // the same load order as in the loop
+      }
+      for (int64_t gb = 0; gb < nring; gb += ATQ_DEPTH) {
+#pragma unroll
+        for (int d = 0; d < ATQ_DEPTH; ++d) {
+          mm(a[d], q[d]);
+          const int64_t nx = gb + ATQ_DEPTH + d;
+          ld(nx < nring ? nx : gb + d, a[d], q[d]);  // past the ring: reloaded, not used
+          // keeps the loads ahead of the next groups' MFMAs (the compiler would otherwise
+          // move them down to their uses)
+          asm volatile("" ::: "memory");
+        }
+      }
     }
-  };
-  double a[4], q[NT];
-  load(r0, a, q);
-  for (int64_t rq = r0; rq < r1; rq += 4) {
-    double an[4], qn[NT];
-    load((rq + 4 < r1) ? rq + 4 : rq, an, qn);
+  } else {
+    const int cvalid = n - cb;
+    auto load = [&](int64_t rq, double (&a)[4], double (&q)[NT]) {
+      const int64_t row = rq + g;
+      const bool rok = row < r1;
+      const int64_t rr = rok ? row : r0;
+      if (rok && cvalid > 0) {
+        load4(A + rr * lda + cb, cvalid >= 4, cvalid, a);
+      } else {
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+        for (int mt = 0; mt < 4; ++mt) a[mt] = 0.0;
+      }
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_f64(a[mt], q[nt], acc[mt][nt]);
+      for (int nt = 0; nt < NT; ++nt) {
+        const int col = 16 * nt + li;
+        q[nt] = (rok && col < l) ? (double)Q[rr * ldq + col] : 0.0;
+      }
+    };
+    double a[4], q[NT];
+    load(r0, a, q);
+    for (int64_t rq = r0; rq < r1; rq += 4) {
+      double an[4], qn[NT];
+      load((rq + 4 < r1) ? rq + 4 : rq, an, qn);
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) a[mt] = an[mt];
+      for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) q[nt] = qn[nt];
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_f64(a[mt], q[nt], acc[mt][nt]);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) a[mt] = an[mt];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) q[nt] = qn[nt];
+    }
   }
   double* P = part + (int64_t)chunk * n * l;
 #pragma unroll
@@ -363,9 +549,13 @@ static void launch_atq(const TA* A, int64_t lda, int64_t m, int64_t n, const TQ*
   atq_grid(m, n, ncol, nchunk, cr);
   const int total = n <= 64 ? (nchunk + 3) / 4 : ncol * nchunk;
   const int grid = ((total + 7) / 8) * 8;
+  const bool vec = ax_vec(A, lda, n);
   if (n <= 64)
     hipLaunchKernelGGL((k_gemm_atq_f64<NT, TA, true, TQ>), dim3(grid), dim3(256), 0, s, A, lda, m,
                        (int)n, Q, ldq, l, ncol, nchunk, cr, part);
+  else if (vec)
+    hipLaunchKernelGGL((k_gemm_atq_f64<NT, TA, false, TQ, true>), dim3(grid), dim3(256), 0, s, A,
+                       lda, m, (int)n, Q, ldq, l, ncol, nchunk, cr, part);
   else
     hipLaunchKernelGGL((k_gemm_atq_f64<NT, TA, false, TQ>), dim3(grid), dim3(256), 0, s, A, lda, m,
                        (int)n, Q, ldq, l, ncol, nchunk, cr, part);
