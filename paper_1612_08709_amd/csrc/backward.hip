@@ -133,7 +133,12 @@ __global__ void k_zero(double* __restrict__ p, int64_t count) {
 // MFMA.  Wave = 32 rows x 64 columns; workgroup = 2 x 2 waves.  Both operands are contiguous
 // along K, so lane (i, g) reads L[row i][k0+4g .. k0+4g+3] and R[col i][k0+4g ..] and uses
 // element s in MFMA s (k-slot g <-> k0 + 4g + s).
-template <typename TC>
+// VEC (rows of L and R start on 16 bytes, K a multiple of 4): the main loop loads without a
+// branch (rows past m and columns past n read the last valid one; those results are not
+// stored) and alternates two register sets, so one step's loads are in flight during the
+// other step's MFMAs; a last step of fewer than 16 (K % 16 = 4, 8 or 12) is done once with
+// a lane condition.
+template <typename TC, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_nt(const double* __restrict__ L, int64_t ldl,
                                                  const double* __restrict__ R, int64_t ldr,
                                                  int64_t m, int64_t n, int K,
@@ -148,29 +153,93 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const double* __restrict__ L, i
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    double x[TM][4], y[TN][4];
+  if constexpr (VEC) {
+    const double* lp[TM];
+    const double* rp[TN];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int kk = k0 + 4 * g + s;
-#pragma unroll
-      for (int a = 0; a < TM; ++a) {
-        const int64_t row = rb + 16 * a + li;
-        x[a][s] = (kk < K && row < m) ? L[row * ldl + kk] : 0.0;
-      }
-#pragma unroll
-      for (int b = 0; b < TN; ++b) {
-        const int64_t col = cb + 16 * b + li;
-        y[b][s] = (kk < K && col < n) ? R[col * ldr + kk] : 0.0;
-      }
+    for (int a = 0; a < TM; ++a) {
+      const int64_t row = rb + 16 * a + li;
+      lp[a] = L + (row < m ? row : m - 1) * ldl + 4 * g;
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int b = 0; b < TN; ++b) {
+      const int64_t col = cb + 16 * b + li;
+      rp[b] = R + (col < n ? col : n - 1) * ldr + 4 * g;
+    }
+    auto ld = [&](int k0, Quad<double> (&x)[TM], Quad<double> (&y)[TN]) {
 #pragma unroll
-      for (int a = 0; a < TM; ++a)
+      for (int a = 0; a < TM; ++a) x[a].load(lp[a] + k0);
 #pragma unroll
-        for (int b = 0; b < TN; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a][s], y[b][s], acc[a][b], 0, 0, 0);
+      for (int b = 0; b < TN; ++b) y[b].load(rp[b] + k0);
+    };
+    auto mm = [&](Quad<double> (&x)[TM], Quad<double> (&y)[TN]) {
+#pragma unroll
+      for (int a = 0; a < TM; ++a) x[a].pin();
+#pragma unroll
+      for (int b = 0; b < TN; ++b) y[b].pin();
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int b = 0; b < TN; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a][s], y[b][s], acc[a][b], 0, 0, 0);
+    };
+    const int nfull = K >> 4;
+    Quad<double> x0[TM], y0[TN], x1[TM], y1[TN];
+    // the partial last step first (straight-line code before the loop keeps the
+    // accumulators in place), with zeros in the lanes past K
+    if (16 * nfull < K) {
+#pragma unroll
+      for (int a = 0; a < TM; ++a) x0[a].zero();
+#pragma unroll
+      for (int b = 0; b < TN; ++b) y0[b].zero();
+      if (16 * nfull + 4 * g < K) ld(16 * nfull, x0, y0);
+      mm(x0, y0);
+    }
+    int st = 0;
+    if (nfull & 1) {
+      ld(0, x0, y0);
+      mm(x0, y0);
+      st = 1;
+    }
+    if (st < nfull) {  // an even number of steps remains
+      ld(16 * st, x0, y0);
+      for (; st < nfull; st += 2) {
+        // the empty asm statements keep each step's loads ahead of the other step's MFMAs
+        ld(16 * (st + 1), x1, y1);
+        asm volatile("" ::: "memory");
+        mm(x0, y0);
+        ld(16 * (st + 2 < nfull ? st + 2 : st + 1), x0, y0);  // the last one is not used
+        asm volatile("" ::: "memory");
+        mm(x1, y1);
+      }
+    }
+  } else {
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      double x[TM][4], y[TN][4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kk = k0 + 4 * g + s;
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+          const int64_t row = rb + 16 * a + li;
+          x[a][s] = (kk < K && row < m) ? L[row * ldl + kk] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          const int64_t col = cb + 16 * b + li;
+          y[b][s] = (kk < K && col < n) ? R[col * ldr + kk] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int b = 0; b < TN; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a][s], y[b][s], acc[a][b], 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int a = 0; a < TM; ++a)
@@ -222,12 +291,24 @@ hipError_t zero_fill(double* p, int64_t count, hipStream_t s) {
 hipError_t gemm_nt(const double* L, int64_t ldl, const double* R, int64_t ldr, int64_t m,
                    int64_t n, int K, void* C, int c_dtype, int64_t ldc, hipStream_t s) {
   dim3 grid((unsigned)((n + 127) / 128), (unsigned)((m + 63) / 64));
-  if (c_dtype == TSSVD_F64)
-    hipLaunchKernelGGL((k_gemm_nt<double>), grid, dim3(256), 0, s, L, ldl, R, ldr, m, n, K,
-                       (double*)C, ldc);
-  else
-    hipLaunchKernelGGL((k_gemm_nt<float>), grid, dim3(256), 0, s, L, ldl, R, ldr, m, n, K,
-                       (float*)C, ldc);
+  const bool vec = (reinterpret_cast<uintptr_t>(L) & 15) == 0 &&
+                   (reinterpret_cast<uintptr_t>(R) & 15) == 0 && ldl % 2 == 0 && ldr % 2 == 0 &&
+                   K % 4 == 0;
+  if (c_dtype == TSSVD_F64) {
+    if (vec)
+      hipLaunchKernelGGL((k_gemm_nt<double, true>), grid, dim3(256), 0, s, L, ldl, R, ldr, m, n,
+                         K, (double*)C, ldc);
+    else
+      hipLaunchKernelGGL((k_gemm_nt<double, false>), grid, dim3(256), 0, s, L, ldl, R, ldr, m, n,
+                         K, (double*)C, ldc);
+  } else {
+    if (vec)
+      hipLaunchKernelGGL((k_gemm_nt<float, true>), grid, dim3(256), 0, s, L, ldl, R, ldr, m, n,
+                         K, (float*)C, ldc);
+    else
+      hipLaunchKernelGGL((k_gemm_nt<float, false>), grid, dim3(256), 0, s, L, ldl, R, ldr, m, n,
+                         K, (float*)C, ldc);
+  }
   return hipGetLastError();
 }
 

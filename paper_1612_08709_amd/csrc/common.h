@@ -58,6 +58,34 @@ __device__ __forceinline__ double sign_ref(int i) {
   return t - floor(t) - 0.5;
 }
 
+// ---- four consecutive entries of a matrix row as one register quad: a 16-byte load for float32,
+// two for float64.  pin() is an empty asm statement that reads and writes the quad, so the
+// float32 -> float64 conversions of one pipeline slot cannot be scheduled above it (they
+// would make the wave wait for the loads of the later slots).
+template <typename TA>
+struct Quad;
+template <>
+struct Quad<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  v4 v;
+  __device__ __forceinline__ void load(const float* p) { v = *reinterpret_cast<const v4*>(p); }
+  __device__ __forceinline__ void zero() { v = v4{0.f, 0.f, 0.f, 0.f}; }
+  __device__ __forceinline__ void pin() { asm volatile("" : "+v"(v)); }
+  __device__ __forceinline__ double operator[](int s) const { return (double)v[s]; }
+};
+template <>
+struct Quad<double> {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  v2 lo, hi;
+  __device__ __forceinline__ void load(const double* p) {
+    lo = *reinterpret_cast<const v2*>(p);
+    hi = *reinterpret_cast<const v2*>(p + 2);
+  }
+  __device__ __forceinline__ void zero() { lo = hi = v2{0.0, 0.0}; }
+  __device__ __forceinline__ void pin() { asm volatile("" : "+v"(lo), "+v"(hi)); }
+  __device__ __forceinline__ double operator[](int s) const { return s < 2 ? lo[s] : hi[s - 2]; }
+};
+
 // numstat bits of tssvd_info
 constexpr int NUM_NONFINITE = 1;
 constexpr int NUM_NO_CONVERGENCE = 2;

@@ -71,34 +71,6 @@ __device__ __forceinline__ void load4(const float* p, bool full, int valid, doub
 // l - 1: those results are never stored.  The steps alternate between two register sets;
 // a last step of fewer than 16 columns (n % 16 = 4, 8 or 12) is done once with a lane
 // condition.
-// Four consecutive entries of a row of A as one register quad: a 16-byte load for float32,
-// two for float64.  pin() is an empty asm statement that reads and writes the quad, so the
-// float32 -> float64 conversions of one pipeline slot cannot be scheduled above it (they
-// would make the wave wait for the loads of the later slots).
-template <typename TA>
-struct Quad;
-template <>
-struct Quad<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  v4 v;
-  __device__ __forceinline__ void load(const float* p) { v = *reinterpret_cast<const v4*>(p); }
-  __device__ __forceinline__ void zero() { v = v4{0.f, 0.f, 0.f, 0.f}; }
-  __device__ __forceinline__ void pin() { asm volatile("" : "+v"(v)); }
-  __device__ __forceinline__ double operator[](int s) const { return (double)v[s]; }
-};
-template <>
-struct Quad<double> {
-  typedef double v2 __attribute__((ext_vector_type(2)));
-  v2 lo, hi;
-  __device__ __forceinline__ void load(const double* p) {
-    lo = *reinterpret_cast<const v2*>(p);
-    hi = *reinterpret_cast<const v2*>(p + 2);
-  }
-  __device__ __forceinline__ void zero() { lo = hi = v2{0.0, 0.0}; }
-  __device__ __forceinline__ void pin() { asm volatile("" : "+v"(lo), "+v"(hi)); }
-  __device__ __forceinline__ double operator[](int s) const { return s < 2 ? lo[s] : hi[s - 2]; }
-};
-
 template <int RT, int NT, typename TA, bool PACK = false, bool VEC = false>
 __global__ __launch_bounds__(256) void k_gemm_ax_f64(const TA* __restrict__ A, int64_t lda,
                                                      int64_t m, int n,

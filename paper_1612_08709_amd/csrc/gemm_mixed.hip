@@ -652,49 +652,13 @@ __device__ __forceinline__ void atq_rows(const float* __restrict__ A, int64_t ld
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) b[pc][nt] = qs[slot][pc * FS + nt * 64 + lane];
   };
+  // Order of the sums (the same in the kernel that reads the bfloat16 copy of A, so the two
+  // agree bit for bit): the ragged last rows first (only the chunk that ends at m; rows past
+  // r1 read as 0, and with no ragged rows the step is all zeros), then the whole 32-row
+  // steps in order, an odd one first on its own.  All MFMAs before the paired loop: MFMAs
+  // after it make the compiler copy the accumulators in and out on every iteration.
   const int64_t rfull = r0 + (((r1 - r0) >> 5) << 5);
-  if constexpr (PIECES == 1) {
-    if (rfull > r0) {
-      // two register sets, two steps in flight (as in Y = A X)
-      float v0[8][4], v1[8][4];
-      bf16x8 x0[FPT], x1[FPT];
-      const int64_t last = rfull - 32;
-      load_a(r0, v0);
-      load_x(r0, x0);
-      const int64_t r1st = (r0 + 32 < last) ? r0 + 32 : last;
-      load_a(r1st, v1);
-      load_x(r1st, x1);
-      bf16x8 a[PIECES][4], b[PIECES][NT];
-      int64_t rb = r0;
-      for (; rb + 64 <= rfull; rb += 64) {
-        stage(0, x0, b);
-        to_pieces_cols<PIECES>(v0, a);
-        __builtin_amdgcn_sched_barrier(0);
-        const int64_t r2 = (rb + 64 < last) ? rb + 64 : last;
-        load_a(r2, v0);
-        load_x(r2, x0);
-        __builtin_amdgcn_sched_barrier(0);
-        mfma_pieces<4, NT, PIECES, false>(a, b, acc);
-        __builtin_amdgcn_sched_barrier(0);
-        stage(1, x1, b);
-        to_pieces_cols<PIECES>(v1, a);
-        __builtin_amdgcn_sched_barrier(0);
-        const int64_t r3 = (rb + 96 < last) ? rb + 96 : last;
-        load_a(r3, v1);
-        load_x(r3, x1);
-        __builtin_amdgcn_sched_barrier(0);
-        mfma_pieces<4, NT, PIECES, false>(a, b, acc);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      if (rb < rfull) {
-        stage(0, x0, b);
-        to_pieces_cols<PIECES>(v0, a);
-        mfma_pieces<4, NT, PIECES, false>(a, b, acc);
-      }
-    }
-  }
-  if (rfull < r1) {
-    // ragged last rows (only the chunk that ends at m): rows past r1 read as 0
+  {
     float v[8][4];
     bf16x8 b[PIECES][NT];
 #pragma unroll
@@ -704,7 +668,7 @@ __device__ __forceinline__ void atq_rows(const float* __restrict__ A, int64_t ld
 #pragma unroll
       for (int e = 0; e < 4; ++e) v[t][e] = (wact && row < r1 && cb + e < n) ? p[e] : 0.f;
     }
-    const int64_t kb = rfull >> 5;
+    const int64_t kb = rfull < r1 ? rfull >> 5 : 0;
 #pragma unroll
     for (int pc = 0; pc < PIECES; ++pc)
 #pragma unroll
@@ -712,6 +676,59 @@ __device__ __forceinline__ void atq_rows(const float* __restrict__ A, int64_t ld
     bf16x8 a[PIECES][4];
     to_pieces_cols<PIECES>(v, a);
     mfma_pieces<4, NT, PIECES, false>(a, b, acc);
+  }
+  const int64_t nsteps = (rfull - r0) >> 5;
+  {
+    float v[8][4];
+    bf16x8 x[FPT], b[PIECES][NT], a[PIECES][4];
+    if (nsteps & 1) {
+      load_a(r0, v);
+      load_x(r0, x);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[t][e] = 0.f;
+#pragma unroll
+      for (int u = 0; u < FPT; ++u) x[u] = __builtin_bit_cast(bf16x8, u32x4v{0u, 0u, 0u, 0u});
+    }
+    stage(1, x, b);  // slot 1: the loop's first barrier comes before its next write
+    to_pieces_cols<PIECES>(v, a);
+    mfma_pieces<4, NT, PIECES, false>(a, b, acc);
+  }
+  if (nsteps > 1) {
+    // two register sets, two steps in flight (as in Y = A X)
+    float v0[8][4], v1[8][4];
+    bf16x8 x0[FPT], x1[FPT];
+    const int64_t last = rfull - 32;
+    const int64_t rs = r0 + 32 * (nsteps & 1);  // first step of the pairs
+    load_a(rs, v0);
+    load_x(rs, x0);
+    __builtin_amdgcn_sched_barrier(0);  // the same load order as in the loop
+    load_a(rs + 32, v1);
+    load_x(rs + 32, x1);
+    __builtin_amdgcn_sched_barrier(0);
+    bf16x8 a[PIECES][4], b[PIECES][NT];
+    for (int64_t rb = rs; rb + 64 <= rfull; rb += 64) {
+      stage(0, x0, b);
+      to_pieces_cols<PIECES>(v0, a);
+      __builtin_amdgcn_sched_barrier(0);
+      const int64_t r2 = (rb + 64 < last) ? rb + 64 : last;
+      load_a(r2, v0);
+      load_x(r2, x0);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_pieces<4, NT, PIECES, false>(a, b, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      stage(1, x1, b);
+      to_pieces_cols<PIECES>(v1, a);
+      __builtin_amdgcn_sched_barrier(0);
+      const int64_t r3 = (rb + 96 < last) ? rb + 96 : last;
+      load_a(r3, v1);
+      load_x(r3, x1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_pieces<4, NT, PIECES, false>(a, b, acc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 }
 
@@ -1036,12 +1053,22 @@ __global__ __launch_bounds__(256) void k_ax_bf16c(const bf16x8* __restrict__ Ac,
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mfma_bf16(a[j][rt], b[j][nt], acc[rt][nt]);
   };
-  // two register sets, two groups in flight (as in k_ax_bf16)
+  // two register sets, two groups in flight (as in k_ax_bf16).  An odd group count does its
+  // first group alone, before the loop (through LDS slot 1, which the loop's first barrier
+  // protects): MFMAs after the loop would make the compiler copy the accumulators in and
+  // out of it on every iteration.
   bf16x8 a0[2][RT], a1[2][RT], x0[FPT], x1[FPT];
   const int last = ngroups - 1;
-  load(0, a0, x0);
-  load(last < 1 ? last : 1, a1, x1);
   int kg = 0;
+  if (ngroups & 1) {
+    load(0, a0, x0);
+    products(1, a0, x0);
+    kg = 1;
+  }
+  load(kg < last ? kg : last, a0, x0);
+  __builtin_amdgcn_sched_barrier(0);  // the same load order as in the loop
+  load(kg + 1 < last ? kg + 1 : last, a1, x1);
+  __builtin_amdgcn_sched_barrier(0);
   for (; kg + 2 <= ngroups; kg += 2) {
     products(0, a0, x0);
     __builtin_amdgcn_sched_barrier(0);
@@ -1052,7 +1079,6 @@ __global__ __launch_bounds__(256) void k_ax_bf16c(const bf16x8* __restrict__ Ac,
     load((kg + 3 < last) ? kg + 3 : last, a1, x1);
     __builtin_amdgcn_sched_barrier(0);
   }
-  if (kg < ngroups) products(0, a0, x0);
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -1094,8 +1120,10 @@ __device__ __forceinline__ void atqc_products(const uint2 (&v)[8], const bf16x8 
 // The Q fragments of a 32-row step (NT*64, contiguous) are shared by the four waves through
 // LDS as in k_ax_bf16c, two steps per barrier, so every wave takes part in the loop; a
 // wave whose columns lie past n reads no A (zeros) and stores nothing.
+// At most two waves per SIMD: with the loads unconditional the kernel fits three, which
+// measured slower on the 500,000 x 8,000 power steps (more streams in flight per channel).
 template <int NT>
-__global__ __launch_bounds__(256) void k_atq_bf16c(const __bf16* __restrict__ Ac, int64_t ldc,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_atq_bf16c(const __bf16* __restrict__ Ac, int64_t ldc,
                                                    int64_t m, int n,
                                                    const bf16x8* __restrict__ Qp, int l,
                                                    int ncol, int nchunk, int64_t chunk_rows,
@@ -1114,8 +1142,10 @@ __global__ __launch_bounds__(256) void k_atq_bf16c(const __bf16* __restrict__ Ac
   const bool wact = cw < n;
   const int64_t r0 = (int64_t)chunk * chunk_rows;  // chunk_rows is a multiple of 32
   const int64_t r1 = (r0 + chunk_rows < m) ? r0 + chunk_rows : m;
+  // lanes past the padded row read its last four entries: their columns are past n, and
+  // results for columns past n are never stored (no lane condition on the loads)
   const int cb = cw + 4 * li;
-  const bool cok = wact && cb < ldc;  // ldc is a multiple of 32, so cb + 4 <= ldc
+  const int cbc = cb < ldc ? cb : ldc - 4;  // ldc is a multiple of 32
   f32x4 acc[4][NT];
 #pragma unroll
   for (int e = 0; e < 4; ++e)
@@ -1129,10 +1159,8 @@ __global__ __launch_bounds__(256) void k_atq_bf16c(const __bf16* __restrict__ Ac
     for (int u = 0; u < FPT; ++u)
       if (FR % 256 == 0 || tid + 256 * u < FR) x[u] = src[tid + 256 * u];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const __bf16* p = Ac + (rb + 8 * g + t) * ldc + cb;
-      v[t] = cok ? *reinterpret_cast<const uint2*>(p) : make_uint2(0u, 0u);
-    }
+    for (int t = 0; t < 8; ++t)
+      v[t] = *reinterpret_cast<const uint2*>(Ac + (rb + 8 * g + t) * ldc + cbc);
   };
   // both steps of a 64-row pair are staged together: one barrier per pair
   auto stage = [&](int slot, const bf16x8 (&x0)[FPT], const bf16x8 (&x1)[FPT]) {
@@ -1150,16 +1178,54 @@ __global__ __launch_bounds__(256) void k_atq_bf16c(const __bf16* __restrict__ Ac
     for (int nt = 0; nt < NT; ++nt) b[nt] = qs[slot][h][nt * 64 + lane];
     atqc_products<NT>(v, b, acc);
   };
+  // The order of the sums is that of atq_rows (which rounds the float32 A to bfloat16 on
+  // the fly), so both give the same bits: everything outside the paired loop first, as
+  // straight-line MFMAs (MFMAs after the loop would make the compiler copy the
+  // accumulators in and out of it on every iteration):
+  //  * the ragged last rows (only the chunk that ends at m), rows past r1 read as 0;
+  //  * with an odd number of whole 32-row steps, the first step alone (through LDS slot 1,
+  //    which the loop's first barrier protects); with an even number a step of zeros.
   const int64_t rfull = r0 + (((r1 - r0) >> 5) << 5);
-  if (rfull > r0) {
+  {
+    uint2 v[8];
+    bf16x8 b[NT];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t row = rfull + 8 * g + t;
+      v[t] = (row < r1 && wact) ? *reinterpret_cast<const uint2*>(Ac + row * ldc + cbc)
+                                : make_uint2(0u, 0u);
+    }
+    const int64_t kb = rfull < r1 ? rfull >> 5 : 0;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) b[nt] = qp[(kb * NT + nt) * 64];
+    atqc_products<NT>(v, b, acc);
+  }
+  const int64_t nsteps = (rfull - r0) >> 5;
+  {
+    uint2 v[8];
+    bf16x8 x[FPT];
+    if (nsteps & 1) {
+      load(r0, v, x);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = make_uint2(0u, 0u);
+#pragma unroll
+      for (int u = 0; u < FPT; ++u) x[u] = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
+    }
+    stage(1, x, x);
+    products(1, 0, v);
+  }
+  if (nsteps > 1) {
     uint2 v0[8], v1[8];
     bf16x8 x0[FPT], x1[FPT];
     const int64_t last = rfull - 32;
-    load(r0, v0, x0);
-    load((r0 + 32 < last) ? r0 + 32 : last, v1, x1);
-    int64_t rb = r0;
+    const int64_t rs = r0 + 32 * (nsteps & 1);  // first step of the pairs
+    load(rs, v0, x0);
+    __builtin_amdgcn_sched_barrier(0);  // the same load order as in the loop
+    load(rs + 32, v1, x1);
+    __builtin_amdgcn_sched_barrier(0);
     int slot = 0;
-    for (; rb + 64 <= rfull; rb += 64) {
+    for (int64_t rb = rs; rb + 64 <= rfull; rb += 64) {
       stage(slot, x0, x1);
       products(slot, 0, v0);
       __builtin_amdgcn_sched_barrier(0);
@@ -1171,27 +1237,8 @@ __global__ __launch_bounds__(256) void k_atq_bf16c(const __bf16* __restrict__ Ac
       __builtin_amdgcn_sched_barrier(0);
       slot ^= 1;
     }
-    if (rb < rfull) {
-      stage(slot, x0, x0);
-      products(slot, 0, v0);
-    }
   }
   if (!wact) return;
-  if (rfull < r1) {
-    // ragged last rows (only the chunk that ends at m): rows past r1 read as 0
-    uint2 v[8];
-    bf16x8 b[NT];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int64_t row = rfull + 8 * g + t;
-      v[t] = (row < r1 && cok) ? *reinterpret_cast<const uint2*>(Ac + row * ldc + cb)
-                               : make_uint2(0u, 0u);
-    }
-    const int64_t kb = rfull >> 5;
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) b[nt] = qp[(kb * NT + nt) * 64];
-    atqc_products<NT>(v, b, acc);
-  }
   double* P = part + (int64_t)chunk * n * l;
 #pragma unroll
   for (int e = 0; e < 4; ++e)
