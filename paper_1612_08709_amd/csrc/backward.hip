@@ -277,6 +277,13 @@ hipError_t bw_qr_coef(const double* M, const double* R, int l, double* Rinv, dou
 hipError_t rmul(const double* X1, int64_t ld1, int k1, const double* K1, const double* X2,
                 int64_t ld2, int k2, const double* K2, int64_t rows, int kout, double* out,
                 int64_t ldo, bool accum, hipStream_t s) {
+  // two passes of the matrix-core product Y (+)= X K when the strides fit its int arguments
+  // (l <= 112 columns), else the plain kernel
+  if (kout <= 112 && ldo <= INT32_MAX) {
+    hipError_t e = gemm_ax_f64_acc(X1, ld1, rows, k1, K1, kout, kout, out, (int)ldo, accum, s);
+    if (e != hipSuccess || !X2 || k2 <= 0) return e;
+    return gemm_ax_f64_acc(X2, ld2, rows, k2, K2, kout, kout, out, (int)ldo, true, s);
+  }
   hipLaunchKernelGGL(k_rmul, dim3(blocks(rows * kout)), dim3(256), 0, s, X1, ld1, k1, K1, X2,
                      ld2, k2, K2, rows, kout, out, ldo, accum ? 1 : 0);
   return hipGetLastError();

@@ -76,7 +76,8 @@ __global__ __launch_bounds__(256) void k_gemm_ax_f64(const TA* __restrict__ A, i
                                                      int64_t m, int n,
                                                      const double* __restrict__ X, int ldx,
                                                      int l, double* __restrict__ Y, int ldy,
-                                                     bf16x8_t* __restrict__ P = nullptr) {
+                                                     bf16x8_t* __restrict__ P = nullptr,
+                                                     int accum = 0) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int64_t rbase = (int64_t)blockIdx.x * (64 * RT) + (int64_t)wave * (16 * RT);
@@ -233,7 +234,8 @@ __global__ __launch_bounds__(256) void k_gemm_ax_f64(const TA* __restrict__ A, i
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = rbase + 16 * rt + 4 * r + g;
-        if (row < m && col < l) Y[row * ldy + col] = acc[rt][nt][r];
+        if (row < m && col < l)
+          Y[row * ldy + col] = accum ? Y[row * ldy + col] + acc[rt][nt][r] : acc[rt][nt][r];
       }
     }
 }
@@ -277,29 +279,29 @@ hipError_t gemm_ax_f64_pack_bf16(const double* Y, int64_t ldy, int64_t m, const 
 
 template <int NT, typename TA>
 static void launch_ax(const TA* A, int64_t lda, int64_t m, int64_t n, const double* X,
-                      int ldx, int l, double* Y, int ldy, hipStream_t s) {
+                      int ldx, int l, double* Y, int ldy, int accum, hipStream_t s) {
   constexpr int RT = 2;
   const int64_t grid = (m + 64 * RT - 1) / (64 * RT);
   if (ax_vec(A, lda, n))
     hipLaunchKernelGGL((k_gemm_ax_f64<RT, NT, TA, false, true>), dim3((unsigned)grid),
-                       dim3(256), 0, s, A, lda, m, (int)n, X, ldx, l, Y, ldy, nullptr);
+                       dim3(256), 0, s, A, lda, m, (int)n, X, ldx, l, Y, ldy, nullptr, accum);
   else
     hipLaunchKernelGGL((k_gemm_ax_f64<RT, NT, TA>), dim3((unsigned)grid), dim3(256), 0, s, A,
-                       lda, m, (int)n, X, ldx, l, Y, ldy, nullptr);
+                       lda, m, (int)n, X, ldx, l, Y, ldy, nullptr, accum);
 }
 
 template <typename TA>
 static hipError_t ax_dispatch(const TA* A, int64_t lda, int64_t m, int64_t n, const double* X,
-                              int ldx, int l, double* Y, int ldy, hipStream_t s) {
+                              int ldx, int l, double* Y, int ldy, int accum, hipStream_t s) {
   const int nt = (l + 15) / 16;
   switch (nt) {
-    case 1: launch_ax<1>(A, lda, m, n, X, ldx, l, Y, ldy, s); break;
-    case 2: launch_ax<2>(A, lda, m, n, X, ldx, l, Y, ldy, s); break;
-    case 3: launch_ax<3>(A, lda, m, n, X, ldx, l, Y, ldy, s); break;
-    case 4: launch_ax<4>(A, lda, m, n, X, ldx, l, Y, ldy, s); break;
-    case 5: launch_ax<5>(A, lda, m, n, X, ldx, l, Y, ldy, s); break;
-    case 6: launch_ax<6>(A, lda, m, n, X, ldx, l, Y, ldy, s); break;
-    case 7: launch_ax<7>(A, lda, m, n, X, ldx, l, Y, ldy, s); break;
+    case 1: launch_ax<1>(A, lda, m, n, X, ldx, l, Y, ldy, accum, s); break;
+    case 2: launch_ax<2>(A, lda, m, n, X, ldx, l, Y, ldy, accum, s); break;
+    case 3: launch_ax<3>(A, lda, m, n, X, ldx, l, Y, ldy, accum, s); break;
+    case 4: launch_ax<4>(A, lda, m, n, X, ldx, l, Y, ldy, accum, s); break;
+    case 5: launch_ax<5>(A, lda, m, n, X, ldx, l, Y, ldy, accum, s); break;
+    case 6: launch_ax<6>(A, lda, m, n, X, ldx, l, Y, ldy, accum, s); break;
+    case 7: launch_ax<7>(A, lda, m, n, X, ldx, l, Y, ldy, accum, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -310,10 +312,15 @@ hipError_t gemm_ax_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int64
                        int prof) {
   prof_begin(prof, s);
   hipError_t e = (a_dtype == TSSVD_F64)
-                     ? ax_dispatch((const double*)A, lda, m, n, X, ldx, l, Y, ldy, s)
-                     : ax_dispatch((const float*)A, lda, m, n, X, ldx, l, Y, ldy, s);
+                     ? ax_dispatch((const double*)A, lda, m, n, X, ldx, l, Y, ldy, 0, s)
+                     : ax_dispatch((const float*)A, lda, m, n, X, ldx, l, Y, ldy, 0, s);
   prof_end(prof, s);
   return e;
+}
+
+hipError_t gemm_ax_f64_acc(const double* A, int64_t lda, int64_t m, int64_t n, const double* X,
+                           int ldx, int l, double* Y, int ldy, bool accum, hipStream_t s) {
+  return ax_dispatch(A, lda, m, n, X, ldx, l, Y, ldy, accum ? 1 : 0, s);
 }
 
 // ---------------------------------------------------------------- Z = A^T Q

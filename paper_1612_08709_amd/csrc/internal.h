@@ -91,6 +91,9 @@ hipError_t jacobi_svd(const double* M, int ldm, int n, int transpose, double wp,
 hipError_t gemm_ax_f64(const void* A, int a_dtype, int64_t lda, int64_t m, int64_t n,
                        const double* X, int ldx, int l, double* Y, int ldy, hipStream_t s,
                        int prof = -1);
+// The same for float64 A with Y += A X when accum (Y read before it is written).
+hipError_t gemm_ax_f64_acc(const double* A, int64_t lda, int64_t m, int64_t n, const double* X,
+                           int ldx, int l, double* Y, int ldy, bool accum, hipStream_t s);
 // Z (n x l, stride ldz) = A^T (n x m) Q (m x l, stride ldq).  Split over row chunks into
 // `part` (size atq_partials(m, n, l) doubles), reduced in a fixed order.
 size_t atq_partials(int64_t m, int64_t n, int l);

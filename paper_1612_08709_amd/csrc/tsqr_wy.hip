@@ -30,6 +30,7 @@
 // instruction lane (i, g) supplies its register s of both (row(s, g)).  Tiles read as A
 // operands from memory are stored "operand-permuted": row i keeps column row(s, g) at
 // position 4g + s, so a lane loads its four k values as one vector.
+#include <cstddef>
 #include <type_traits>
 
 #include "common.h"
@@ -223,7 +224,7 @@ struct WyShared {
   CT Wbr[wch<NT>()][4][64];        // -T_p^T W of the round's tiles
   CT slot[2][WWAVES][16];          // per-wave partial column dots (panel steps)
   CT ZT[16][16];                   // v_k^T v_j (k < j) of the panel, then T_p (row-major)
-  CT tau[16];
+  CT tau[16];                      // directly after ZT (read as ZT[16][0..15])
 };
 
 }  // namespace
@@ -361,13 +362,21 @@ __global__ __launch_bounds__(WTHREADS, sizeof(CT) == 4 ? 4 : 2) void k_wy_factor
 #pragma unroll
         for (int r = 0; r < 4; ++r) sh.R[utile(p, p, NT)][r][lane] = rd[r];
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        // ZT and tau through a base address held in a vector register: the reads below then
+        // use constant offsets (with the constant shared-memory addresses the compiler
+        // builds every one of the 136 addresses separately, out of spilled scalars)
+        using Sh = WyShared<CT, NT>;
+        static_assert(offsetof(Sh, tau) == offsetof(Sh, ZT) + 256 * sizeof(CT),
+                      "tau must follow ZT");
+        const CT* zt = &sh.ZT[0][0];
+        asm volatile("" : "+v"(zt));
         CT trow[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           CT t = zero;
 #pragma unroll
-          for (int k = 0; k < j; ++k) t = fma(trow[k], sh.ZT[k][j], t);
-          const CT tj = sh.tau[j];
+          for (int k = 0; k < j; ++k) t = fma(trow[k], zt[16 * k + j], t);
+          const CT tj = zt[256 + j];  // tau follows ZT
           trow[j] = (j >= nj) ? zero : (li < j) ? -tj * t : (li == j ? tj : zero);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
