@@ -14,32 +14,40 @@ constexpr int CH = 8;  // independent accumulator chains per wave
 // CH independent v_mfma_f64_16x16x4_f64 chains per wave, `iters` rounds.
 __global__ __launch_bounds__(256) void k_mfma_f64(int iters, double* out) {
   const double a = 1.0 + 1e-3 * (threadIdx.x & 63), b = 1.0 - 1e-3 * (threadIdx.x & 15);
+  // the first round outside the loop: the loop then carries matrix-core results only
   f64x4 acc[CH];
 #pragma unroll
-  for (int c = 0; c < CH; ++c) acc[c] = f64x4{0.0, 0.0, 0.0, (double)c};
-  for (int i = 0; i < iters; ++i) {
+  for (int c = 0; c < CH; ++c)
+    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, f64x4{0.0, 0.0, 0.0, (double)c}, 0, 0, 0);
+  for (int i = 1; i < iters; ++i) {
 #pragma unroll
     for (int c = 0; c < CH; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
   }
-  double s = 0.0;
+  // keeps the chains alive (never true).  Storing the accumulators as they are, rather than
+  // adding them up, lets them stay in the matrix-core registers: a sum after the loop makes
+  // the compiler copy them out and back in on every round, which halves the rate measured.
+  if (iters < 0) {
 #pragma unroll
-  for (int c = 0; c < CH; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
-  if (s == 12345.678) out[blockIdx.x] = s;  // keeps the chains alive; never true
+    for (int c = 0; c < CH; ++c)
+      reinterpret_cast<f64x4*>(out)[(blockIdx.x * 256 + threadIdx.x) * CH + c] = acc[c];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_mfma_f32(int iters, double* out) {
   const float a = 1.0f + 1e-3f * (threadIdx.x & 63), b = 1.0f - 1e-3f * (threadIdx.x & 15);
   f32x4 acc[CH];
 #pragma unroll
-  for (int c = 0; c < CH; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, (float)c};
-  for (int i = 0; i < iters; ++i) {
+  for (int c = 0; c < CH; ++c)
+    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, f32x4{0.f, 0.f, 0.f, (float)c}, 0, 0, 0);
+  for (int i = 1; i < iters; ++i) {
 #pragma unroll
     for (int c = 0; c < CH; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
   }
-  float s = 0.f;
+  if (iters < 0) {  // as in k_mfma_f64
 #pragma unroll
-  for (int c = 0; c < CH; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
-  if (s == 12345.678f) out[blockIdx.x] = s;
+    for (int c = 0; c < CH; ++c)
+      reinterpret_cast<f32x4*>(out)[(blockIdx.x * 256 + threadIdx.x) * CH + c] = acc[c];
+  }
 }
 
 // 2*CH independent FP64 FMA chains per lane.
@@ -67,13 +75,17 @@ __global__ __launch_bounds__(256) void k_mix_f64(int iters, int valu_iters, doub
     const double a = 1.0 + 1e-3 * (threadIdx.x & 63), b = 1.0 - 1e-3 * (threadIdx.x & 15);
     f64x4 acc[CH];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) acc[c] = f64x4{0.0, 0.0, 0.0, (double)c};
-    for (int i = 0; i < iters; ++i) {
+    for (int c = 0; c < CH; ++c)
+      acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, f64x4{0.0, 0.0, 0.0, (double)c}, 0, 0, 0);
+    for (int i = 1; i < iters; ++i) {
 #pragma unroll
       for (int c = 0; c < CH; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
     }
+    if (iters < 0) {  // as in k_mfma_f64
 #pragma unroll
-    for (int c = 0; c < CH; ++c) s += acc[c][0] + acc[c][3];
+      for (int c = 0; c < CH; ++c)
+        reinterpret_cast<f64x4*>(out)[(blockIdx.x * 256 + threadIdx.x) * CH + c] = acc[c];
+    }
   } else {
     double x[2 * CH];
     const double m = 1.0 + 1e-9 * threadIdx.x, a = 1e-7;
