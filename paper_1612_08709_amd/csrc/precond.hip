@@ -278,8 +278,9 @@ __global__ __launch_bounds__(PC_THREADS, 1) void k_pc_trsm(
 // the operand tiles live in the local data share, so two workgroups share a CU, and each
 // wave solves two 16-row tiles whose dependent chains of matrix-core steps interleave.
 // Chunks of 128 rows (4 waves x 32) go to the workgroups in turn.  Same in-place rule as
-// k_pc_trsm.
-template <int NT, typename TA, bool VEC>
+// k_pc_trsm.  Element-wise accesses (rows not 16-byte aligned or n not a multiple of 4;
+// otherwise k_pc_trsm_pipe below).
+template <int NT, typename TA>
 __global__ __launch_bounds__(PC_THREADS, 2) void k_pc_trsm2(
     const TA* X, int64_t ldx, int64_t m, int n, const double* __restrict__ Rop, double* Q,
     int64_t ldq, const int* __restrict__ gate) {
@@ -310,17 +311,12 @@ __global__ __launch_bounds__(PC_THREADS, 2) void k_pc_trsm2(
 #pragma unroll
     for (int J = 0; J < NT; ++J) {
       d4 acc[2];
-      const int c0 = 16 * J + 4 * g;  // groups of four are whole: n % 4 == 0 when VEC
+      const int c0 = 16 * J + 4 * g;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (VEC) {
-          ld4<true>(xr[h] + c0, rok[h] && c0 < n, acc[h]);
-        } else {
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            acc[h][r] = (rok[h] && c0 + r < n) ? (double)xr[h][c0 + r] : 0.0;
-        }
-      }
+        for (int r = 0; r < 4; ++r)
+          acc[h][r] = (rok[h] && c0 + r < n) ? (double)xr[h][c0 + r] : 0.0;
 #pragma unroll
       for (int K = 0; K < J; ++K) {
         const double* op = Rs + upk(K, J, NT) * 256 + lane;
@@ -347,15 +343,84 @@ __global__ __launch_bounds__(PC_THREADS, 2) void k_pc_trsm2(
 #pragma unroll
       for (int J = 0; J < NT; ++J) {
         const int c0 = 16 * J + 4 * g;
-        if (VEC) {
-          if (rok[h] && c0 < n) st4<true>(qr + c0, q[h][J]);
-        } else {
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (rok[h] && c0 + r < n) qr[c0 + r] = q[h][J][r];
-        }
+        for (int r = 0; r < 4; ++r)
+          if (rok[h] && c0 + r < n) qr[c0 + r] = q[h][J][r];
       }
     }
+  }
+}
+
+// The solve alone for 16-byte aligned rows and n a multiple of 4, pipelined: a wave takes 16
+// rows per 64-row chunk (lane i: row i, four adjacent columns per tile, as above) and loads
+// the rows of its next chunk, with no branch, while it solves the current one.  Rows past m
+// read row m - 1 and columns past n the last four columns (their results are not stored;
+// the padding of Rop is the identity).
+template <int NT, typename TA>
+__global__ __launch_bounds__(PC_THREADS, 2) void k_pc_trsm_pipe(
+    const TA* X, int64_t ldx, int64_t m, int n, const double* __restrict__ Rop, double* Q,
+    int64_t ldq, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  constexpr int NTT = pc_pairs<NT>();
+  extern __shared__ double smem[];
+  double* Rs = smem;  // NTT * 256
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  for (int i = tid; i < NTT * 256; i += PC_THREADS) Rs[i] = Rop[i];
+  __syncthreads();
+  const int64_t nchunk = (m + PC_CHUNK - 1) / PC_CHUNK;
+  int64_t ch = blockIdx.x;
+  if (ch >= nchunk) return;
+  int cc[NT];
+#pragma unroll
+  for (int J = 0; J < NT; ++J) cc[J] = (16 * J + 4 * g < n) ? 16 * J + 4 * g : n - 4;
+  auto ld = [&](int64_t c, Quad<TA> (&xv)[NT]) {
+    const int64_t row = c * PC_CHUNK + 16 * wave + li;
+    const TA* xr = X + (row < m ? row : m - 1) * ldx;
+#pragma unroll
+    for (int J = 0; J < NT; ++J) xv[J].load(xr + cc[J]);
+  };
+  auto solve = [&](int64_t c, Quad<TA> (&xv)[NT]) {
+    // the operand tiles are read per use (the compiler would otherwise hoist them all out
+    // of the chunk loop and spill them)
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int J = 0; J < NT; ++J) xv[J].pin();
+    const int64_t row = c * PC_CHUNK + 16 * wave + li;
+    d4 q[NT];
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+      d4 acc = {xv[J][0], xv[J][1], xv[J][2], xv[J][3]};
+#pragma unroll
+      for (int K = 0; K < J; ++K) {
+        const double* op = Rs + upk(K, J, NT) * 256 + lane;
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) acc = mma(op[64 * s2], q[K][s2], acc);
+      }
+      const double* od = Rs + upk(J, J, NT) * 256 + lane;
+      q[J] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) q[J] = mma(od[64 * s2], acc[s2], q[J]);
+    }
+    if (row < m) {
+      double* qr = Q + row * ldq;
+#pragma unroll
+      for (int J = 0; J < NT; ++J)
+        if (16 * J + 4 * g < n) st4<true>(qr + 16 * J + 4 * g, q[J]);
+    }
+  };
+  Quad<TA> xa[NT], xb[NT];
+  ld(ch, xa);
+  for (;;) {
+    const int64_t c1 = ch + gridDim.x;
+    ld(c1 < nchunk ? c1 : ch, xb);  // past the end: reloaded, not used
+    solve(ch, xa);
+    if (c1 >= nchunk) break;
+    const int64_t c2 = c1 + gridDim.x;
+    ld(c2 < nchunk ? c2 : c1, xa);
+    solve(c1, xb);
+    if (c2 >= nchunk) break;
+    ch = c2;
   }
 }
 
@@ -409,6 +474,76 @@ __global__ __launch_bounds__(PC_THREADS, 1) void k_rowmul(double* X, int64_t ldx
         if (rowy < m && col < n) X[rowy * ldx + col] = y[r];
       }
     }
+  }
+}
+
+// The same product for 16-byte aligned rows and n a multiple of 4, pipelined: eight waves
+// (one workgroup per CU, the 16 x 16-tile operand N in the local data share) and 128-row
+// chunks; the rows of a wave's next chunk are loaded, with no branch, while the current
+// chunk's tiles are formed.  Rows past m read row m - 1 and columns past n the last four
+// columns; their results are not stored, and the padding rows of N are zero.
+constexpr int RM_THREADS = 512;
+constexpr int RM_CHUNK = 128;
+
+template <int NT>
+__global__ __launch_bounds__(RM_THREADS, 1) void k_rowmul_pipe(double* X, int64_t ldx,
+                                                               int64_t m, int n,
+                                                               const double* __restrict__ Nop,
+                                                               const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  extern __shared__ double Ns[];  // NT * NT * 256
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  for (int i = tid; i < NT * NT * 256; i += RM_THREADS) Ns[i] = Nop[i];
+  __syncthreads();
+  const int64_t nchunk = (m + RM_CHUNK - 1) / RM_CHUNK;
+  int64_t ch = blockIdx.x;
+  if (ch >= nchunk) return;
+  int cc[NT];
+#pragma unroll
+  for (int K = 0; K < NT; ++K) cc[K] = (16 * K + 4 * g < n) ? 16 * K + 4 * g : n - 4;
+  auto ld = [&](int64_t c, Quad<double> (&xv)[NT]) {
+    const int64_t row = c * RM_CHUNK + 16 * wave + li;
+    const double* xa = X + (row < m ? row : m - 1) * ldx;
+#pragma unroll
+    for (int K = 0; K < NT; ++K) xv[K].load(xa + cc[K]);
+  };
+  auto form = [&](int64_t c, Quad<double> (&xv)[NT]) {
+    // the operand tiles are read per use: without the barrier the compiler would hoist all
+    // of them out of the chunk loop (they do not change) and spill them
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int K = 0; K < NT; ++K) xv[K].pin();
+    const int64_t r0 = c * RM_CHUNK + 16 * wave;
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+      d4 y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int K = 0; K < NT; ++K) {
+        const double* op = Ns + (K * NT + J) * 256 + lane;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) y = mma(xv[K][s], op[64 * s], y);
+      }
+      const int col = 16 * J + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t rowy = r0 + 4 * r + g;
+        if (rowy < m && col < n) X[rowy * ldx + col] = y[r];
+      }
+    }
+  };
+  Quad<double> xa[NT], xb[NT];
+  ld(ch, xa);
+  for (;;) {
+    const int64_t c1 = ch + gridDim.x;
+    ld(c1 < nchunk ? c1 : ch, xb);  // past the end: reloaded, not used
+    form(ch, xa);
+    if (c1 >= nchunk) break;
+    const int64_t c2 = c1 + gridDim.x;
+    ld(c2 < nchunk ? c2 : c1, xa);
+    form(c1, xb);
+    if (c2 >= nchunk) break;
+    ch = c2;
   }
 }
 
@@ -510,10 +645,10 @@ hipError_t pc_launch_nt(const double* R, int ldr, int n, double tol, double* Rp,
     e = hipFuncSetAttribute((const void*)k_pc_trsm<NT, double>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)trsm_lds<NT>());
     if (e != hipSuccess) return e;
-    const void* k2[4] = {(const void*)k_pc_trsm2<NT, float, false>,
-                         (const void*)k_pc_trsm2<NT, float, true>,
-                         (const void*)k_pc_trsm2<NT, double, false>,
-                         (const void*)k_pc_trsm2<NT, double, true>};
+    const void* k2[4] = {(const void*)k_pc_trsm2<NT, float>,
+                         (const void*)k_pc_trsm_pipe<NT, float>,
+                         (const void*)k_pc_trsm2<NT, double>,
+                         (const void*)k_pc_trsm_pipe<NT, double>};
     for (const void* f : k2) {
       e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
       if (e != hipSuccess) return e;
@@ -539,6 +674,8 @@ hipError_t pc_launch_nt(const double* R, int ldr, int n, double tol, double* Rp,
   } else {
     const int64_t nch = (m + 2 * PC_CHUNK - 1) / (2 * PC_CHUNK);
     const int grid = (int)(nch < 2 * PC_GRID_MAX ? (nch > 0 ? nch : 1) : 2 * PC_GRID_MAX);
+    const int64_t nch1 = (m + PC_CHUNK - 1) / PC_CHUNK;  // the pipelined kernel's chunks
+    const int grid1 = (int)(nch1 < 2 * PC_GRID_MAX ? (nch1 > 0 ? nch1 : 1) : 2 * PC_GRID_MAX);
     // vector accesses when every row of X and Q starts on 16 bytes and n is whole fours
     const size_t xs = x_dtype == TSSVD_F32 ? 4 : 8;
     const bool vec = n % 4 == 0 && (reinterpret_cast<uintptr_t>(Xv) & 15) == 0 &&
@@ -546,17 +683,17 @@ hipError_t pc_launch_nt(const double* R, int ldr, int n, double tol, double* Rp,
                      (ldq * 8) % 16 == 0;
     if (x_dtype == TSSVD_F32) {
       if (vec)
-        hipLaunchKernelGGL((k_pc_trsm2<NT, float, true>), dim3(grid), dim3(PC_THREADS), lds2,
+        hipLaunchKernelGGL((k_pc_trsm_pipe<NT, float>), dim3(grid1), dim3(PC_THREADS), lds2,
                            s, (const float*)Xv, ldx, m, n, Rop, Q, ldq, gate);
       else
-        hipLaunchKernelGGL((k_pc_trsm2<NT, float, false>), dim3(grid), dim3(PC_THREADS), lds2,
+        hipLaunchKernelGGL((k_pc_trsm2<NT, float>), dim3(grid), dim3(PC_THREADS), lds2,
                            s, (const float*)Xv, ldx, m, n, Rop, Q, ldq, gate);
     } else {
       if (vec)
-        hipLaunchKernelGGL((k_pc_trsm2<NT, double, true>), dim3(grid), dim3(PC_THREADS), lds2,
+        hipLaunchKernelGGL((k_pc_trsm_pipe<NT, double>), dim3(grid1), dim3(PC_THREADS), lds2,
                            s, (const double*)Xv, ldx, m, n, Rop, Q, ldq, gate);
       else
-        hipLaunchKernelGGL((k_pc_trsm2<NT, double, false>), dim3(grid), dim3(PC_THREADS), lds2,
+        hipLaunchKernelGGL((k_pc_trsm2<NT, double>), dim3(grid), dim3(PC_THREADS), lds2,
                            s, (const double*)Xv, ldx, m, n, Rop, Q, ldq, gate);
     }
   }
@@ -581,10 +718,19 @@ hipError_t rowmul_nt(double* X, int64_t ldx, int64_t m, int n, const double* N, 
                      ldn, n, Nop);
   // vector loads when every row of X starts on 16 bytes and n is whole fours
   const bool vec = n % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0 && ldx % 2 == 0;
-  if (vec)
-    hipLaunchKernelGGL((k_rowmul<NT, true>), dim3(grid), dim3(PC_THREADS), lds, s, X, ldx, m,
-                       n, Nop, gate);
-  else
+  if (vec) {
+    static bool attr2 = false;
+    if (!attr2) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_rowmul_pipe<NT>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      attr2 = true;
+    }
+    const int64_t nch = (m + RM_CHUNK - 1) / RM_CHUNK;
+    const int g2 = (int)(nch < PC_GRID_MAX ? (nch > 0 ? nch : 1) : PC_GRID_MAX);
+    hipLaunchKernelGGL((k_rowmul_pipe<NT>), dim3(g2), dim3(RM_THREADS), lds, s, X, ldx, m, n,
+                       Nop, gate);
+  } else
     hipLaunchKernelGGL((k_rowmul<NT, false>), dim3(grid), dim3(PC_THREADS), lds, s, X, ldx, m,
                        n, Nop, gate);
   return hipGetLastError();

@@ -362,14 +362,15 @@ __global__ __launch_bounds__(WTHREADS, sizeof(CT) == 4 ? 4 : 2) void k_wy_factor
 #pragma unroll
         for (int r = 0; r < 4; ++r) sh.R[utile(p, p, NT)][r][lane] = rd[r];
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        // ZT and tau through a base address held in a vector register: the reads below then
-        // use constant offsets (with the constant shared-memory addresses the compiler
-        // builds every one of the 136 addresses separately, out of spilled scalars)
+        // float64: ZT and tau through a base address held in a vector register, so the reads
+        // below use constant offsets (with the constant shared-memory addresses the compiler
+        // builds every one of the 136 addresses separately, out of spilled scalars).  In
+        // float32 the register pressure elsewhere is such that this measured slower.
         using Sh = WyShared<CT, NT>;
         static_assert(offsetof(Sh, tau) == offsetof(Sh, ZT) + 256 * sizeof(CT),
                       "tau must follow ZT");
         const CT* zt = &sh.ZT[0][0];
-        asm volatile("" : "+v"(zt));
+        if constexpr (sizeof(CT) == 8) asm volatile("" : "+v"(zt));
         CT trow[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
