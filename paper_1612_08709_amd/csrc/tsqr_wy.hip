@@ -18,7 +18,8 @@
 //
 // Apply pass (U = Q [S; 0] for a seed S from the merge tree): Q_t [S; 0] = [S - W; -V W]
 // with W = T S, and W is found panel by panel from the last one back,
-//   W_p = T_p (S_p - sum_{q > p} Z_pq W_q),
+//   W_p = T_p (S_p - sum_{q > p} Z_pq W_q)
+// (each W_q is subtracted from the sums of the earlier panels as soon as it is formed),
 // so each block costs a small n x n x k recurrence plus one 128 x n x k product that
 // writes the block's rows of U; the seed of the block before is S - W.
 //
@@ -560,73 +561,97 @@ __global__ __launch_bounds__(64 * WA_WAVES) void k_wy_apply(
     }
   const int64_t b0 = (int64_t)blockIdx.x * bpw;
   const int64_t b1 = (b0 + bpw < nblocks) ? b0 + bpw : nblocks;
-  auto stage_zt = [&](int64_t blk) {
+  // ZS: the next block's tiles are loaded into registers at the start of a block and put
+  // into the local data share after its phase 2 (one memory latency per block, hidden
+  // behind the block's work, instead of one per staged element)
+  constexpr int ZPT = (NZT * 256 + 64 * WA_WAVES - 1) / (64 * WA_WAVES);
+  CT zreg[ZS ? ZPT : 1];
+  auto fetch_zt = [&](int64_t blk) {
     const CT* Zb = Zg + blk * (int64_t)(NPAIR > 0 ? NPAIR : 1) * 256;
     const CT* Tb = Tg + blk * (int64_t)NT * 256;
-    for (int i = tid; i < NZT * 256; i += 64 * WA_WAVES)
-      ZTl[i] = (i < NPAIR * 256) ? Zb[i] : Tb[i - NPAIR * 256];
+#pragma unroll
+    for (int u = 0; u < ZPT; ++u) {
+      int i = tid + 64 * WA_WAVES * u;
+      i = i < NZT * 256 ? i : NZT * 256 - 1;
+      zreg[u] = *((i < NPAIR * 256) ? Zb + i : Tb + (i - NPAIR * 256));
+    }
+  };
+  auto put_zt = [&]() {
+#pragma unroll
+    for (int u = 0; u < ZPT; ++u) {
+      const int i = tid + 64 * WA_WAVES * u;
+      if (i < NZT * 256) ZTl[i] = zreg[u];
+    }
   };
   if constexpr (ZS) {
-    if (b1 > b0) stage_zt(b1 - 1);
+    if (b1 > b0) {
+      fetch_zt(b1 - 1);
+      put_zt();
+    }
     __syncthreads();
   }
+  // every load so far has landed: the compiler's wait counts inside the block loop then
+  // track only that loop's own loads (otherwise the seed loads above, on the path that skips
+  // the staging, make it wait for each block's V rows before phase 1)
+  __builtin_amdgcn_s_waitcnt(0);
   for (int64_t blk = b1 - 1; blk >= b0; --blk) {
     const CT* Vb = Vg + blk * (int64_t)WB * LDV;
     const CT* Zb = ZS ? ZTl : Zg + blk * (int64_t)(NPAIR > 0 ? NPAIR : 1) * 256;
     const CT* Tb = ZS ? ZTl + NPAIR * 256 : Tg + blk * (int64_t)NT * 256;
-    // this wave's rows of V (phase 2), as A operands: row 16 wave + i, 16-column group q
+    // this wave's rows of V (phase 2), as A operands: row 16 wave + i, 16-column group q.
+    // All NT groups are loaded, with no condition (a row holds 16 NT elements); groups
+    // q >= np are never used.  Then the next block's staged tiles, after them: waiting for
+    // these rows in phase 2 does not wait for those.
     CT va[NT][4];
     {
       // rows of V are 16-byte aligned (the workspace is, and a row is 16 NT elements)
       const CT* vr = Vb + (int64_t)(16 * wave + li) * LDV + 4 * g;
 #pragma unroll
-      for (int q = 0; q < NT; ++q) {
-        if (q < np) {
-          load4_aligned(vr + 16 * q, va[q]);
-        } else {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) va[q][t] = zero;
-        }
-      }
+      for (int q = 0; q < NT; ++q) load4_aligned(vr + 16 * q, va[q]);
     }
-    // ---- phase 1: W = T S, last panel first
+    if constexpr (ZS) fetch_zt(blk > b0 ? blk - 1 : blk);  // no branch: the last is unused
+    // ---- phase 1: W = T S, last panel first.  Each W_q, once formed, is pushed at once into
+    // the sums of the panels before it (acc_q' -= Z_q'q W_q, independent accumulators), so
+    // the dependent chain is one panel's T product and one Z product per step instead of
+    // all of a panel's Z products.  Tiles of W past the panels in use are never read.
     if (cwave) {
-      CT wq[NT][4];
-#pragma unroll
-      for (int q = NT - 1; q >= 0; --q) {
-        if (q >= np) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) wq[q][r] = zero;
-        } else {
-          v4 acc = {s[q][0], s[q][1], s[q][2], s[q][3]};
-#pragma unroll
-          for (int q2 = q + 1; q2 < NT; ++q2) {
-            if (q2 >= np) continue;
-            const CT* zr = Zb + upair(q, q2, NT) * 256 + li * 16 + 4 * g;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) acc = L::mma(-zr[t], wq[q2][t], acc);
-          }
-          const CT* tr = Tb + q * 256 + li * 16 + 4 * g;
-          v4 wv = {zero, zero, zero, zero};
-#pragma unroll
-          for (int t = 0; t < 4; ++t) wv = L::mma(tr[t], acc[t], wv);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) wq[q][r] = wv[r];
-        }
-      }
+      CT ac[NT][4];
 #pragma unroll
       for (int q = 0; q < NT; ++q)
 #pragma unroll
+        for (int r = 0; r < 4; ++r) ac[q][r] = s[q][r];
+#pragma unroll
+      for (int q = NT - 1; q >= 0; --q) {
+        if (q >= np) continue;
+        const CT* tr = Tb + q * 256 + li * 16 + 4 * g;
+        v4 wv = {zero, zero, zero, zero};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) wv = L::mma(tr[t], ac[q][t], wv);
+#pragma unroll
         for (int r = 0; r < 4; ++r) {
-          Wl[((q * NT + wave) * 4 + r) * 64 + lane] = wq[q][r];
-          s[q][r] -= wq[q][r];
+          Wl[((q * NT + wave) * 4 + r) * 64 + lane] = wv[r];
+          s[q][r] -= wv[r];
         }
+#pragma unroll
+        for (int q2 = 0; q2 < q; ++q2) {
+          const CT* zr = Zb + upair(q2, q, NT) * 256 + li * 16 + 4 * g;
+          v4 a = {ac[q2][0], ac[q2][1], ac[q2][2], ac[q2][3]};
+#pragma unroll
+          for (int t = 0; t < 4; ++t) a = L::mma(-zr[t], wv[t], a);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) ac[q2][r] = a[r];
+        }
+      }
     }
     __syncthreads();
     // ---- phase 2: rows 16 wave .. 16 wave + 15 of U = -V W
     const int64_t row0 = blk * WB + 16 * wave;
     if (row0 < m) {
-      for (int J = 0; J < ncw; ++J) {
+      // unrolled (a loop here would make the compiler wait for the staged tiles' loads too,
+      // at its entry)
+#pragma unroll
+      for (int J = 0; J < NT; ++J) {
+        if (J >= ncw) break;
         v4 u = {zero, zero, zero, zero};
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
@@ -646,7 +671,7 @@ __global__ __launch_bounds__(64 * WA_WAVES) void k_wy_apply(
       }
     }
     if constexpr (ZS) {
-      if (blk > b0) stage_zt(blk - 1);  // phase 1 of this block has read the staged tiles
+      if (blk > b0) put_zt();  // phase 1 of this block has read the staged tiles
     }
     __syncthreads();  // before the next block's phase 1 reads them and overwrites W
   }
