@@ -245,7 +245,9 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
  * implemented forward map with Omega held fixed (Omega == NULL: the Philox sketch of
  * opts->seed).  The forward is recomputed from (A, Omega) inside the call with one
  * orthonormalization per factorization (a second pass on an orthonormal factor has
- * identity derivative), so U, S, V must come from lowrank_svd on the same A, Omega, k,
+ * identity derivative): the intermediate bases as lowrank_svd forms them (CholeskyQR,
+ * with the device gate to the TSQR), the last one by the TSQR; U, S, V must therefore
+ * come from lowrank_svd on the same A, Omega, k,
  * l, q and options; they are not read.  2q+2 passes over A recompute the forward, 2q+1
  * passes and one m x (2q+2)l x n product form gA.
  *   gA : m x n, a_dtype, stride ldga (written)

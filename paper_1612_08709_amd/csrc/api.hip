@@ -1310,8 +1310,10 @@ namespace {
 struct BackwardWs {
   TsqrPlan pY, pZ;
   int K2;
+  // Rj, Rtj: R^-1 of each factorization (the QR layer of the reverse pass needs only that)
   double *Lcat, *Rcat, *Rj, *Rtj, *Y, *Z, *Xbar, *Qtbar, *I, *Ub, *sig, *Ws, *Wfull, *G1, *G2,
       *A1, *KB, *Kw, *Kv, *UbkT, *M, *Rinv, *K1, *K2m, *part;
+  int* flags;  // basis gate: [0] the TSQR branch was taken, [1] the Cholesky failed, [2] unused
   size_t bytes;
 };
 
@@ -1353,17 +1355,18 @@ BackwardWs backward_layout(int64_t m, int64_t n, int k, int l, int q, void* work
   for (size_t x : cand)
     if (x > np) np = x;
   w.part = c.take<double>(np);
+  w.flags = c.take<int>(4);
   w.bytes = c.off + 256;
   return w;
 }
 
-// Ybar = [Xbar - Qx copyltu(Xbar^T Qx)] R^-T, written to out (rows x l, stride ldo).
+// Ybar = [Xbar - Qx copyltu(Xbar^T Qx)] R^-T, written to out (rows x l, stride ldo); Ri = R^-1.
 hipError_t qr_back(BackwardWs& w, const double* Xbar, int64_t ldx, const double* Qx, int64_t ldq,
-                   const double* R, int64_t rows, int l, double* out, int64_t ldo,
+                   const double* Ri, int64_t rows, int l, double* out, int64_t ldo,
                    hipStream_t s) {
   hipError_t e = gemm_atq_f64(Xbar, TSSVD_F64, ldx, rows, l, Qx, (int)ldq, l, w.M, l, w.part, s);
   if (e != hipSuccess) return e;
-  e = bw_qr_coef(w.M, R, l, w.Rinv, w.K1, w.K2m, s);
+  e = bw_qr_coef_rinv(w.M, Ri, l, w.K1, w.K2m, s);
   if (e != hipSuccess) return e;
   return rmul(Xbar, ldx, l, w.K1, Qx, ldq, l, w.K2m, rows, l, out, ldo, false, s);
 }
@@ -1416,19 +1419,32 @@ int lowrank_svd_backward(const void* A, int32_t a_dtype, int64_t m, int64_t n, i
     TRY(philox_sketch(w.Z, n, li, o.seed, s));
     TRY(copy_matrix(w.Z, n, li, l, Rblk(1), K2, s));
   }
+  // The intermediate bases as the forward takes them (the CholeskyQR basis of Algorithm 7
+  // with the device gate to the TSQR, reading 14): Q = Y T with T = R^-1, kept as the QR
+  // layer's R^-1.  When the gate takes the TSQR branch, T = I, Y holds the Householder Q,
+  // and R^-1 is formed from the TSQR's R by the same gated inverse kernel.
+  TRY(chol_rinv_attrs());
+  auto basis = [&](const TsqrPlan& p, double* Yb, int64_t rows, double* Ri,
+                   double* Qout) -> hipError_t {
+    hipError_t e = basis_via_r(p, Yb, rows, li, w.I, Ri, w.M, w.K1, w.part, w.flags, s);
+    if (e != hipSuccess) return e;
+    e = gemm_ax_f64(Yb, TSSVD_F64, l, rows, l, Ri, li, li, Qout, K2, s);  // Q = Y T
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), ll * sizeof(double), s,
+                       tsqr_root(p), li, 1e300, Ri, w.flags + 2, (const int*)nullptr,
+                       (const int*)w.flags);  // TSQR branch: R^-1 of its R (T was I)
+    return hipGetLastError();
+  };
   for (int j = 1; j <= qi; ++j) {
     TRY(gemm_ax_f64(A, a_dtype, lda, m, n, Rblk(j), K2, li, w.Y, li, s));
-    TRY(tsqr_factor(w.pY, w.Y, TSSVD_F64, l, s));
-    TRY(copy_matrix(tsqr_root(w.pY), l, li, l, w.Rj + (j - 1) * ll, l, s));
-    TRY(tsqr_apply(w.pY, w.I, li, Lblk(qi + 1 + j), K2, s));               // Q_j
+    TRY(basis(w.pY, w.Y, m, w.Rj + (j - 1) * ll, Lblk(qi + 1 + j)));         // Q_j
     TRY(gemm_atq_f64(A, a_dtype, lda, m, n, Lblk(qi + 1 + j), K2, li, w.Z, li, w.part, s));
-    TRY(tsqr_factor(w.pZ, w.Z, TSSVD_F64, l, s));
-    TRY(copy_matrix(tsqr_root(w.pZ), l, li, l, w.Rtj + (j - 1) * ll, l, s));
-    TRY(tsqr_apply(w.pZ, w.I, li, Rblk(1 + j), K2, s));                    // Q~_j
+    TRY(basis(w.pZ, w.Z, n, w.Rtj + (j - 1) * ll, Rblk(1 + j)));             // Q~_j
   }
+  // the last basis by the TSQR (Algorithm 7, one orthonormalization), its R inverted
   TRY(gemm_ax_f64(A, a_dtype, lda, m, n, Rblk(1 + qi), K2, li, w.Y, li, s));
   TRY(tsqr_factor(w.pY, w.Y, TSSVD_F64, l, s));
-  TRY(copy_matrix(tsqr_root(w.pY), l, li, l, w.Rj + qi * ll, l, s));
+  TRY(bw_rinv(tsqr_root(w.pY), li, w.Rj + qi * ll, s));
   TRY(tsqr_apply(w.pY, w.I, li, Lblk(0), K2, s));                          // Q
   TRY(gemm_atq_f64(A, a_dtype, lda, m, n, Lblk(0), K2, li, w.Z, li, w.part, s));  // B^T
   TRY(tsqr_factor(w.pZ, w.Z, TSSVD_F64, l, s));

@@ -267,9 +267,14 @@ hipError_t bw_svd_core(const double* Ub, const double* sig, const double* G1, co
   return hipGetLastError();
 }
 
-hipError_t bw_qr_coef(const double* M, const double* R, int l, double* Rinv, double* K1,
-                      double* K2, hipStream_t s) {
+
+hipError_t bw_rinv(const double* R, int l, double* Rinv, hipStream_t s) {
   hipLaunchKernelGGL(k_bw_rinv, dim3(1), dim3(128), 0, s, R, l, Rinv);
+  return hipGetLastError();
+}
+
+hipError_t bw_qr_coef_rinv(const double* M, const double* Rinv, int l, double* K1, double* K2,
+                           hipStream_t s) {
   hipLaunchKernelGGL(k_bw_qrcoef, dim3(blocks(l * l)), dim3(256), 0, s, M, Rinv, l, K1, K2);
   return hipGetLastError();
 }

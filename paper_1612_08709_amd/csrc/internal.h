@@ -189,8 +189,11 @@ hipError_t pc_combine(const int* fl, const double* Rp, const double* R2, const d
 hipError_t bw_svd_core(const double* Ub, const double* sig, const double* G1, const double* G2,
                        const double* Sbar, int l, int k, double* A1, double* KB, double* Kw,
                        double* Kv, double* UbkT, hipStream_t s);
-hipError_t bw_qr_coef(const double* M, const double* R, int l, double* Rinv, double* K1,
-                      double* K2, hipStream_t s);
+// Rinv = R^-1 (upper triangular l x l, stride l; back substitution, one thread per column).
+hipError_t bw_rinv(const double* R, int l, double* Rinv, hipStream_t s);
+// The same from R^-1 (upper triangular, stride l) already formed.
+hipError_t bw_qr_coef_rinv(const double* M, const double* Rinv, int l, double* K1, double* K2,
+                           hipStream_t s);
 hipError_t rmul(const double* X1, int64_t ld1, int k1, const double* K1, const double* X2,
                 int64_t ld2, int k2, const double* K2, int64_t rows, int kout, double* out,
                 int64_t ldo, bool accum, hipStream_t s);
