@@ -117,53 +117,115 @@ __global__ __launch_bounds__(256) void k_ortho_gate(const double* __restrict__ G
 }
 
 // R with R^T R = G (Cholesky, R upper triangular, row-major l x l) for the Gram G = Y^T Y of
-// an intermediate basis.  One workgroup, G in LDS, right-looking with one barrier per step:
-// step k writes row k of R (G_kj / sqrt(G_kk)) and updates the trailing upper triangle,
-// G_ij -= G_ki G_kj / G_kk, on a 16 x 16 thread grid.  *bad = 1 when a pivot is not
-// positive and finite (then R is left unspecified).
+// an intermediate basis.  One workgroup of 256 threads on a 16 x 16 grid, right-looking:
+// thread (ti, tj) keeps the entries G_ij, i = ti + 16a, j = tj + 16b (i <= j), in registers.
+// At step k the 16 threads of row group ti = k % 16 (one 16-lane row of a wave) take the
+// pivot G_kk from its owner by a lane shuffle, write row k of R (G_kj / sqrt(G_kk)) and put
+// the row G_k. and 1 / G_kk in a double-buffered LDS row; after one barrier every thread
+// updates its entries, G_ij -= (G_ki / G_kk) G_kj.  *bad = 1 when a pivot is not positive
+// and finite (then R is left unspecified).
 // With `dead` given (l flags, written), a pivot <= dead_tol G_kk (the squared sine of the
 // angle between column k of Y and the span of the earlier columns) drops direction k: row k
 // of R stays zero and there is no trailing update, so Y = Q R still holds with the dropped
 // column's coefficients in column k of R, and Q has no column k; dead[k] = 1 marks it.
 // With `gate` given and *gate == 0 the kernel does nothing (a step that is not taken).
+template <int NB>  // NB = ceil(l / 16)
 __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ G, int l,
                                               double* __restrict__ R, int* __restrict__ bad,
                                               double dead_tol, int* __restrict__ dead,
                                               const int* __restrict__ gate) {
-  extern __shared__ double Gs[];  // l x l, row-major
+  __shared__ double rowbuf[2][16 * NB];
+  __shared__ double sinv[2];
+  __shared__ int sstat[2];  // 0: pivot taken, 1: direction dropped, 2: failed
   __shared__ unsigned char sdead[TSSVD_N_MAX];
+  __shared__ double sdiag[TSSVD_N_MAX];  // G_kk as given, for the drop test
   if (gate && *gate == 0) return;  // uniform over the workgroup
   const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
-  for (int i = tid; i < l * l; i += 256) {
-    Gs[i] = G[i];
-    R[i] = 0.0;
+  for (int i = tid; i < l * l; i += 256) R[i] = 0.0;
+  for (int i = tid; i < l; i += 256) {
+    sdead[i] = 0;
+    sdiag[i] = G[i * l + i];
   }
-  for (int i = tid; i < l; i += 256) sdead[i] = 0;
-  __syncthreads();
+  __syncthreads();  // the zeros land before any row of R or any dead flag is written
+  double g[NB][NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = ti + 16 * a, j = tj + 16 * b;
+      g[a][b] = (i < l && j < l && i <= j) ? G[i * l + j] : 0.0;
+    }
   int fail = 0;
-  for (int k = 0; k < l; ++k) {
-    const double piv = Gs[k * l + k];
-    if (dead && piv <= dead_tol * G[k * l + k]) {  // uniform, as below
-      if (tid == 0) sdead[k] = 1;
+#pragma unroll
+  for (int ka = 0; ka < NB; ++ka) {
+    for (int kr = 0; kr < 16; ++kr) {
+      const int k = 16 * ka + kr;
+      if (k >= l) break;  // uniform
+      const int buf = k & 1;
+      if (ti == kr) {  // row group of k: one 16-lane row of a wave
+        const double piv = __shfl(g[ka][ka], kr, 16);
+        int st = 0;
+        if (dead && piv <= dead_tol * sdiag[k])
+          st = 1;
+        else if (!(piv > 0.0) || !isfinite(piv))
+          st = 2;
+        const double rd = 1.0 / sqrt(piv), inv = 1.0 / piv;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int j = tj + 16 * b;
+          if (j < l) {
+            const double v = (j >= k && st == 0) ? g[ka][b] : 0.0;
+            rowbuf[buf][j] = v;
+            if (st == 0 && j >= k) R[k * l + j] = g[ka][b] * rd;
+          }
+        }
+        if (tj == 0) {
+          sinv[buf] = inv;
+          sstat[buf] = st;
+          if (st == 1) sdead[k] = 1;
+        }
+      }
       __syncthreads();
-      continue;
+      const int st = sstat[buf];
+      if (st == 2) {  // uniform
+        fail = 1;
+        break;
+      }
+      if (st == 1) continue;
+      const double inv = sinv[buf];
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        const int i = ti + 16 * a;
+        if (i <= k || i >= l) continue;
+        const double gki = rowbuf[buf][i] * inv;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int j = tj + 16 * b;
+          if (j >= i && j < l) g[a][b] = fma(-gki, rowbuf[buf][j], g[a][b]);
+        }
+      }
     }
-    if (!(piv > 0.0) || !isfinite(piv)) {  // uniform: every thread reads the same pivot
-      fail = 1;
-      break;
-    }
-    const double rd = 1.0 / sqrt(piv), inv = 1.0 / piv;
-    for (int j = k + tid; j < l; j += 256) R[k * l + j] = Gs[k * l + j] * rd;
-    for (int i = k + 1 + ti; i < l; i += 16) {
-      const double gki = Gs[k * l + i] * inv;
-      for (int j = k + 1 + tj; j < l; j += 16)
-        if (j >= i) Gs[i * l + j] = fma(-gki, Gs[k * l + j], Gs[i * l + j]);
-    }
-    __syncthreads();
+    if (fail) break;  // uniform
   }
+  __syncthreads();
   if (dead)
     for (int i = tid; i < l; i += 256) dead[i] = sdead[i];
   if (tid == 0) *bad = fail;
+}
+
+hipError_t launch_chol(const double* G, int l, double* R, int* bad, double dead_tol, int* dead,
+                       const int* gate, hipStream_t s) {
+  switch ((l + 15) / 16) {
+    case 1: hipLaunchKernelGGL(k_chol<1>, dim3(1), dim3(256), 0, s, G, l, R, bad, dead_tol, dead, gate); break;
+    case 2: hipLaunchKernelGGL(k_chol<2>, dim3(1), dim3(256), 0, s, G, l, R, bad, dead_tol, dead, gate); break;
+    case 3: hipLaunchKernelGGL(k_chol<3>, dim3(1), dim3(256), 0, s, G, l, R, bad, dead_tol, dead, gate); break;
+    case 4: hipLaunchKernelGGL(k_chol<4>, dim3(1), dim3(256), 0, s, G, l, R, bad, dead_tol, dead, gate); break;
+    case 5: hipLaunchKernelGGL(k_chol<5>, dim3(1), dim3(256), 0, s, G, l, R, bad, dead_tol, dead, gate); break;
+    case 6: hipLaunchKernelGGL(k_chol<6>, dim3(1), dim3(256), 0, s, G, l, R, bad, dead_tol, dead, gate); break;
+    case 7: hipLaunchKernelGGL(k_chol<7>, dim3(1), dim3(256), 0, s, G, l, R, bad, dead_tol, dead, gate); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // Rm = R with each dropped direction's column replaced by e_k (row k of R is zero): the
@@ -651,9 +713,6 @@ hipError_t chol_rinv_attrs() {
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      160 * 1024 - 8192);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          160 * 1024 - 8192);
-  if (e != hipSuccess) return e;
   attr_set = true;
   return hipSuccess;
 }
@@ -711,8 +770,7 @@ hipError_t tssvd_mixed(const void* A, int64_t m, int ni, int64_t lda, double* U,
                      o.reorth_tol, w.ortho, w.gate, info);               // gate = 1
   MTRY(chol_rinv_attrs());
   const size_t lds = (size_t)ni * ni * sizeof(double);
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), lds, s, w.G, ni, w.Rc, w.mflags,
-                     kMixedDeadSine2, w.mdead, (const int*)nullptr);  // R2 (kept columns)
+  MTRY(launch_chol(w.G, ni, w.Rc, w.mflags, kMixedDeadSine2, w.mdead, nullptr, s));  // R2
   hipLaunchKernelGGL(k_unit_dead, dim3(nb), dim3(256), 0, s, w.Rc, w.mdead, ni, w.Rcm,
                      (const int*)nullptr);
   hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), lds, s, w.Rcm, ni, 1e300, w.Ri,
@@ -723,8 +781,7 @@ hipError_t tssvd_mixed(const void* A, int64_t m, int ni, int64_t lda, double* U,
   const int* g2 = w.mflags + 2;
   MTRY(pc_trsm_gram(w.Rcm, ni, ni, kPcClamp, w.Rp2, w.op, U, TSSVD_F64, ldu, m, U, ldu,
                     w.pcpart, w.G2, g2, s));
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), lds, s, w.G2, ni, w.R3, w.mflags + 3,
-                     kMixedDeadSine2, w.mdead2, g2);
+  MTRY(launch_chol(w.G2, ni, w.R3, w.mflags + 3, kMixedDeadSine2, w.mdead2, g2, s));
   hipLaunchKernelGGL(k_unit_dead, dim3(nb), dim3(256), 0, s, w.R3, w.mdead2, ni, w.R3m, g2);
   hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), lds, s, w.R3m, ni, 1e300, w.R3i,
                      w.mflags + 1, (const int*)nullptr, g2);
@@ -1107,8 +1164,8 @@ hipError_t basis_via_r(const TsqrPlan& p, double* Y, int64_t rows, int l, const 
     hipLaunchKernelGGL(k_chol_rinv_gate<64>, dim3(1), dim3(64), 0, s, G, l, kmax, T, use_q,
                        chol_bad);
   } else {
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), (size_t)l * l * sizeof(double), s, G, l, Rc,
-                       chol_bad, 0.0, (int*)nullptr, (const int*)nullptr);
+    e = launch_chol(G, l, Rc, chol_bad, 0.0, nullptr, nullptr, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), (size_t)l * l * sizeof(double),
                        s, Rc, l, kmax, T, use_q, chol_bad, (const int*)nullptr);
   }
