@@ -120,10 +120,11 @@ __global__ __launch_bounds__(256) void k_ortho_gate(const double* __restrict__ G
 // an intermediate basis.  One workgroup of 256 threads on a 16 x 16 grid, right-looking:
 // thread (ti, tj) keeps the entries G_ij, i = ti + 16a, j = tj + 16b (i <= j), in registers.
 // At step k the 16 threads of row group ti = k % 16 (one 16-lane row of a wave) take the
-// pivot G_kk from its owner by a lane shuffle, write row k of R (G_kj / sqrt(G_kk)) and put
-// the row G_k. and 1 / G_kk in a double-buffered LDS row; after one barrier every thread
-// updates its entries, G_ij -= (G_ki / G_kk) G_kj.  *bad = 1 when a pivot is not positive
-// and finite (then R is left unspecified).
+// pivot G_kk from its owner by a lane shuffle, put the row G_k. and 1 / G_kk in a
+// double-buffered LDS row and turn its own entries of row k into row k of R (G_kj /
+// sqrt(G_kk)); after one barrier every thread updates its entries, G_ij -= (G_ki / G_kk) G_kj.
+// R leaves the registers once, at the end, so no barrier waits on global stores.  *bad = 1
+// when a pivot is not positive and finite (then R is left unspecified).
 // With `dead` given (l flags, written), a pivot <= dead_tol G_kk (the squared sine of the
 // angle between column k of Y and the span of the earlier columns) drops direction k: row k
 // of R stays zero and there is no trailing update, so Y = Q R still holds with the dropped
@@ -141,12 +142,11 @@ __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ G, int 
   __shared__ double sdiag[TSSVD_N_MAX];  // G_kk as given, for the drop test
   if (gate && *gate == 0) return;  // uniform over the workgroup
   const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
-  for (int i = tid; i < l * l; i += 256) R[i] = 0.0;
   for (int i = tid; i < l; i += 256) {
     sdead[i] = 0;
     sdiag[i] = G[i * l + i];
   }
-  __syncthreads();  // the zeros land before any row of R or any dead flag is written
+  __syncthreads();  // the zeros land before any dead flag is written
   double g[NB][NB];
 #pragma unroll
   for (int a = 0; a < NB; ++a)
@@ -176,7 +176,9 @@ __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ G, int 
           if (j < l) {
             const double v = (j >= k && st == 0) ? g[ka][b] : 0.0;
             rowbuf[buf][j] = v;
-            if (st == 0 && j >= k) R[k * l + j] = g[ka][b] * rd;
+            // row k of R, kept in place until the end (zero for a dropped direction, whose
+            // pivot may be 0 or negative)
+            g[ka][b] = (j >= k && st == 0) ? v * rd : 0.0;
           }
         }
         if (tj == 0) {
@@ -207,6 +209,14 @@ __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ G, int 
     }
     if (fail) break;  // uniform
   }
+  // R: the rows each thread holds, zero below the diagonal
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = ti + 16 * a, j = tj + 16 * b;
+      if (i < l && j < l) R[i * l + j] = (i <= j) ? g[a][b] : 0.0;
+    }
   __syncthreads();
   if (dead)
     for (int i = tid; i < l; i += 256) dead[i] = sdead[i];

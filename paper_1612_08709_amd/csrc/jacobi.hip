@@ -23,7 +23,10 @@ namespace tsv {
 
 // NT threads = NT / 16 lane groups, at least one per column pair of a round (n <= 2 NT / 16):
 // 1024 for n <= 128, 512 for n <= 64, where each round's barrier then spans 8 waves, not 16.
-template <int NT, int NPL = (2 * NT / 16 + 15) / 16>  // NPL: entries per lane, n <= 16 NPL
+// NPL = ceil(n / 16) entries of a column per lane: only the last of them can fall past row
+// n - 1, so every other load and store is unconditional, and a lane whose last entry lies
+// past the end reads row n - 1 in its place, uses zero for it and stores nothing there.
+template <int NT, int NPL>
 __global__ __launch_bounds__(NT) void k_jacobi(
     const double* __restrict__ M0, int ldm, int n, int transpose, double wp, int max_sweeps,
     int sign_fix, double* __restrict__ Uo, double* __restrict__ So, double* __restrict__ Vo,
@@ -95,18 +98,37 @@ __global__ __launch_bounds__(NT) void k_jacobi(
         if (q < n) {
           double* mp = M + p * n;
           double* mq = M + q * n;
-          // the pair's entries stay in registers from the dot products to the rotation
-          double xr[NPL], yr[NPL];
+          double* vp = V + p * n;
+          double* vq = V + q * n;
+          const int il = lane16 + 16 * (NPL - 1);
+          const bool lv = il < n;  // the last entry is a row of the matrix
+          const int ilc = lv ? il : n - 1;
+          // the pair's entries of M and V stay in registers from the dot products to the
+          // rotation; the V loads are in flight during the reductions
+          double xr[NPL], yr[NPL], vxr[NPL], vyr[NPL];
+#pragma unroll
+          for (int k = 0; k < NPL; ++k) {
+            const int i = (k == NPL - 1) ? ilc : lane16 + 16 * k;
+            xr[k] = mp[i];
+            yr[k] = mq[i];
+          }
+#pragma unroll
+          for (int k = 0; k < NPL; ++k) {
+            const int i = (k == NPL - 1) ? ilc : lane16 + 16 * k;
+            vxr[k] = vp[i];
+            vyr[k] = vq[i];
+          }
+          asm volatile("" ::: "memory");  // issue the V loads here, not after the reductions
+          if (!lv) {
+            xr[NPL - 1] = 0.0;
+            yr[NPL - 1] = 0.0;
+          }
           double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
           for (int k = 0; k < NPL; ++k) {
-            const int i = lane16 + 16 * k;
-            const double x = (i < n) ? mp[i] : 0.0, y = (i < n) ? mq[i] : 0.0;
-            xr[k] = x;
-            yr[k] = y;
-            al = fma(x, x, al);
-            be = fma(y, y, be);
-            ga = fma(x, y, ga);
+            al = fma(xr[k], xr[k], al);
+            be = fma(yr[k], yr[k], be);
+            ga = fma(xr[k], yr[k], ga);
           }
           al = sum16(al);
           be = sum16(be);
@@ -120,17 +142,14 @@ __global__ __launch_bounds__(NT) void k_jacobi(
             const double tt = (d >= 0.0 ? g2 : -g2) / (fabs(d) + sqrt(fma(d, d, g2 * g2)));
             const double c = rsqrt(fma(tt, tt, 1.0));
             const double s = c * tt;
-            double* vp = V + p * n;
-            double* vq = V + q * n;
 #pragma unroll
             for (int k = 0; k < NPL; ++k) {
               const int i = lane16 + 16 * k;
-              if (i < n) {
-                const double vx = vp[i], vy = vq[i];
+              if (k < NPL - 1 || lv) {
                 mp[i] = fma(c, xr[k], -s * yr[k]);
                 mq[i] = fma(s, xr[k], c * yr[k]);
-                vp[i] = fma(c, vx, -s * vy);
-                vq[i] = fma(s, vx, c * vy);
+                vp[i] = fma(c, vxr[k], -s * vyr[k]);
+                vq[i] = fma(s, vxr[k], c * vyr[k]);
               }
             }
             if (lane16 == 0) s_rot = 1;
@@ -138,6 +157,7 @@ __global__ __launch_bounds__(NT) void k_jacobi(
         }
       }
       __syncthreads();
+
     }
     ++sweep;
     converged = (s_rot == 0);
@@ -193,29 +213,44 @@ __global__ __launch_bounds__(NT) void k_jacobi(
   }
 }
 
+template <int NT, int NPL>
+hipError_t launch_jacobi(size_t lds, const double* M, int ldm, int n, int transpose, double wp,
+                         int max_sweeps, int sign_fix, double* Uo, double* So, double* Vo,
+                         tssvd_info* info, hipStream_t s, const int* gate, const double* dsrc,
+                         int ldd) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    const int mx = (int)(2 * TSSVD_N_MAX * TSSVD_N_MAX * sizeof(double));
+    const hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<NT, NPL>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_jacobi<NT, NPL>), dim3(1), dim3(NT), lds, s, M, ldm, n, transpose, wp,
+                     max_sweeps, sign_fix, Uo, So, Vo, info, gate, dsrc, ldd);
+  return hipGetLastError();
+}
+
 hipError_t jacobi_svd(const double* M, int ldm, int n, int transpose, double wp,
                       int max_sweeps, int sign_fix, double* Uo, double* So, double* Vo,
                       tssvd_info* info, hipStream_t s, const int* gate,
                       const double* dsrc, int ldd) {
   const size_t lds = (size_t)2 * n * n * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {
-    const int mx = (int)(2 * TSSVD_N_MAX * TSSVD_N_MAX * sizeof(double));
-    hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<1024>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_jacobi<512>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    if (e != hipSuccess) return e;
-    attr_set = true;
+#define TSV_JAC(NT, NPL)                                                                    \
+  return launch_jacobi<NT, NPL>(lds, M, ldm, n, transpose, wp, max_sweeps, sign_fix, Uo, So, \
+                                Vo, info, s, gate, dsrc, ldd)
+  switch ((n + 15) / 16) {
+    case 0:
+    case 1: TSV_JAC(512, 1);
+    case 2: TSV_JAC(512, 2);
+    case 3: TSV_JAC(512, 3);
+    case 4: TSV_JAC(512, 4);
+    case 5: TSV_JAC(1024, 5);
+    case 6: TSV_JAC(1024, 6);
+    case 7: TSV_JAC(1024, 7);
+    default: return hipErrorInvalidValue;
   }
-  if (n <= 64)
-    hipLaunchKernelGGL(k_jacobi<512>, dim3(1), dim3(512), lds, s, M, ldm, n, transpose, wp,
-                       max_sweeps, sign_fix, Uo, So, Vo, info, gate, dsrc, ldd);
-  else
-    hipLaunchKernelGGL(k_jacobi<1024>, dim3(1), dim3(1024), lds, s, M, ldm, n, transpose, wp,
-                       max_sweeps, sign_fix, Uo, So, Vo, info, gate, dsrc, ldd);
-  return hipGetLastError();
+#undef TSV_JAC
 }
 
 }  // namespace tsv
