@@ -194,16 +194,25 @@ __global__ __launch_bounds__(256) void k_chol(const double* __restrict__ G, int 
         break;
       }
       if (st == 1) continue;
+      // branch-free update: the row's entries are read once, blocks a, b < ka hold rows or
+      // columns before k (nothing to do), and the rest select between old and new value
       const double inv = sinv[buf];
+      double ri[NB], rj[NB];
 #pragma unroll
-      for (int a = 0; a < NB; ++a) {
+      for (int a = ka; a < NB; ++a) {
+        ri[a] = rowbuf[buf][ti + 16 * a];
+        rj[a] = rowbuf[buf][tj + 16 * a];
+      }
+#pragma unroll
+      for (int a = ka; a < NB; ++a) {
         const int i = ti + 16 * a;
-        if (i <= k || i >= l) continue;
-        const double gki = rowbuf[buf][i] * inv;
+        const bool live = i > k && i < l;
+        const double gki = ri[a] * inv;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
+        for (int b = a; b < NB; ++b) {
           const int j = tj + 16 * b;
-          if (j >= i && j < l) g[a][b] = fma(-gki, rowbuf[buf][j], g[a][b]);
+          const double nv = fma(-gki, rj[b], g[a][b]);
+          g[a][b] = (live && j >= i && j < l) ? nv : g[a][b];
         }
       }
     }

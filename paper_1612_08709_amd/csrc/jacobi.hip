@@ -21,6 +21,30 @@
 
 namespace tsv {
 
+// The three 16-lane sums of a pair (|x|^2, |y|^2, x.y) level by level, so the three DPP
+// chains interleave.  Each stage adds the partner lane's value as sum16 does (same operands,
+// same order, bitwise the same sums); the DPP moves take no old value (bound_ctrl, every
+// source lane exists), which saves a register clear per move.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mv(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ void stage3(double& a, double& b, double& c) {
+  const double pa = dpp_mv<CTRL>(a), pb = dpp_mv<CTRL>(b), pc = dpp_mv<CTRL>(c);
+  a += pa;
+  b += pb;
+  c += pc;
+}
+__device__ __forceinline__ void sum16x3(double& a, double& b, double& c) {
+  stage3<0xB1>(a, b, c);   // quad_perm [1,0,3,2]
+  stage3<0x4E>(a, b, c);   // quad_perm [2,3,0,1]
+  stage3<0x141>(a, b, c);  // row_half_mirror
+  stage3<0x140>(a, b, c);  // row_mirror
+}
+
 // NT threads = NT / 16 lane groups, at least one per column pair of a round (n <= 2 NT / 16):
 // 1024 for n <= 128, 512 for n <= 64, where each round's barrier then spans 8 waves, not 16.
 // NPL = ceil(n / 16) entries of a column per lane: only the last of them can fall past row
@@ -130,9 +154,7 @@ __global__ __launch_bounds__(NT) void k_jacobi(
             be = fma(yr[k], yr[k], be);
             ga = fma(xr[k], yr[k], ga);
           }
-          al = sum16(al);
-          be = sum16(be);
-          ga = sum16(ga);
+          sum16x3(al, be, ga);
           // rotate when |ga| > tol sqrt(al be), tested on squares (no square roots).
           // tan(theta) = 2 ga sign(d) / (|d| + sqrt(d^2 + 4 ga^2)), d = be - al: the smaller
           // root of t^2 + 2 zeta t - 1 = 0 with zeta = d / (2 ga), one division.
