@@ -1161,17 +1161,12 @@ hipError_t gram_basis(const double* Y, int64_t rows, int l, double wp, int sweep
 }
 
 constexpr double kKappaMax = 1e4;
-hipError_t basis_via_r(const TsqrPlan& p, double* Y, int64_t rows, int l, const double* I,
-                       double* T, double* G, double* Rc, double* part, int* flags,
-                       hipStream_t s, double wp = 0.0) {
-  int* use_q = flags;
-  int* chol_bad = flags + 1;
-  // wp > 0 (the paper's discard): every basis is the TSQR's Householder Q, with the
-  // discard applied on its R; kappa_max = 0 makes the device gate take that branch
-  const double kmax = (wp > 0.0) ? 0.0 : kKappaMax;
-  hipError_t e = gemm_atq_f64(Y, TSSVD_F64, l, rows, l, Y, l, l, G, l, part, s);  // Y^T Y
-  if (e != hipSuccess) return e;
-  e = chol_rinv_attrs();
+// T = R^-1 for the Cholesky factor R^T R = G, with the kappa gate of k_rinv_gate (*use_q = 1
+// and T = I when ||R||_F ||R^-1||_F > kmax or the factorization fails, *chol_bad = 1 for the
+// latter).  Rc: l x l scratch (l > 64).
+hipError_t chol_rinv(const double* G, int l, double kmax, double* T, int* use_q, int* chol_bad,
+                     double* Rc, hipStream_t s) {
+  hipError_t e = chol_rinv_attrs();
   if (e != hipSuccess) return e;
   if (l <= 16) {
     hipLaunchKernelGGL(k_chol_rinv_gate<16>, dim3(1), dim3(64), 0, s, G, l, kmax, T, use_q,
@@ -1188,6 +1183,29 @@ hipError_t basis_via_r(const TsqrPlan& p, double* Y, int64_t rows, int l, const 
     hipLaunchKernelGGL(k_rinv_gate, dim3(1), dim3(RINV_THREADS), (size_t)l * l * sizeof(double),
                        s, Rc, l, kmax, T, use_q, chol_bad, (const int*)nullptr);
   }
+  return hipGetLastError();
+}
+
+// With *gate == 0 (the second orthonormalization is not taken): T = I and *use_q = 0.
+__global__ void k_gate_identity(const int* __restrict__ gate, double* __restrict__ T, int l,
+                                int* __restrict__ use_q) {
+  if (*gate != 0) return;
+  for (int i = threadIdx.x; i < l * l; i += blockDim.x) T[i] = (i / l == i % l) ? 1.0 : 0.0;
+  if (threadIdx.x == 0) *use_q = 0;
+}
+
+hipError_t basis_via_r(const TsqrPlan& p, double* Y, int64_t rows, int l, const double* I,
+                       double* T, double* G, double* Rc, double* part, int* flags,
+                       hipStream_t s, double wp = 0.0) {
+  int* use_q = flags;
+  int* chol_bad = flags + 1;
+  // wp > 0 (the paper's discard): every basis is the TSQR's Householder Q, with the
+  // discard applied on its R; kappa_max = 0 makes the device gate take that branch
+  const double kmax = (wp > 0.0) ? 0.0 : kKappaMax;
+  hipError_t e = gemm_atq_f64(Y, TSSVD_F64, l, rows, l, Y, l, l, G, l, part, s);  // Y^T Y
+  if (e != hipSuccess) return e;
+  e = chol_rinv(G, l, kmax, T, use_q, chol_bad, Rc, s);
+  if (e != hipSuccess) return e;
   TsqrPlan pq = p;
   pq.gate = use_q;
   e = tsqr_factor(pq, Y, TSSVD_F64, l, s);
@@ -1331,6 +1349,9 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
     TRY(gemm_ax_f64(w.Z, TSSVD_F64, l, n, l, w.Tq, li, li, w.X, li, s));
     TRY(ax(w.X, j == q - 1));                                                  // A Q~_j
   }
+  // the last basis by CholeskyQR twice (Algorithm 2 form) unless a discard rule, Algorithm 8,
+  // LU tracking or a single orthonormalization (ONCE: the TSQR's Q) is asked for
+  const bool cqr_last = !gram && !lu && !(wp > 0.0) && o.ortho != TSSVD_ORTHO_ONCE;
   if (gram) {
     // Algorithm 4 on the last Y: Y1 = Y T1 (Algorithm 3), then Q = Y1 T2 (Algorithm 3 on Y1);
     // the kept rank of the second pass bounds the rank of the result
@@ -1340,13 +1361,31 @@ int lowrank_svd(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t ld
     TRY(gram_basis(Y1, m, li, o.working_precision, o.max_jacobi_sweeps, w.G, w.W, w.P, w.sig,
                    w.Y, w.gsum, w.gnrm, w.gscale, w.gpos, grank, w.Tq, w.part, info, s));
     TRY(gemm_ax_f64(Y1, TSSVD_F64, l, m, l, w.Tq, li, li, w.Y, li, s));      // Q
+  } else if (cqr_last) {
+    // Algorithm 2's two orthonormalizations on the last Y, both as CholeskyQR (each gated to
+    // the TSQR like the intermediate bases): Q1 = Y R1^-1 (into Y1), G = Q1^T Q1 decides the
+    // second one as in tssvd, Q = Q1 R2^-1 (T2 = I when it is not taken).  A failed second
+    // Cholesky leaves T2 = I and the gated TSQR orthonormalizes Q in place.
+    double* Y1 = w.pY.Vleaf;
+    TRY(basis(w.pY, w.Y, m));                                                  // T1 = R1^-1
+    TRY(gemm_ax_f64(w.Y, TSSVD_F64, l, m, l, w.Tq, li, li, Y1, li, s));      // Q1
+    TRY(gemm_atq_f64(Y1, TSSVD_F64, l, m, l, Y1, li, li, w.G, li, w.part, s));
+    hipLaunchKernelGGL(k_ortho_gate, dim3(1), dim3(256), 0, s, w.G, li, o.ortho, o.reorth_tol,
+                       w.ortho, w.gate, info);
+    TRY(chol_rinv(w.G, li, kKappaMax, w.Tq, use_q, use_q + 1, w.Rc, s));     // T2 = R2^-1
+    hipLaunchKernelGGL(k_gate_identity, dim3(1), dim3(256), 0, s, w.gate, w.Tq, li, use_q);
+    TRY(gemm_ax_f64(Y1, TSSVD_F64, l, m, l, w.Tq, li, li, w.Y, li, s));      // Q
+    TsqrPlan p2 = w.pY;
+    p2.gate = use_q;
+    TRY(tsqr_factor(p2, w.Y, TSSVD_F64, l, s));
+    TRY(tsqr_apply(p2, w.I, li, w.Y, l, s));
   } else {
     TRY(orth_inplace(w.pY, w.Y, li, w.I, s));                                  // Q
     if (wp > 0.0)
       hipLaunchKernelGGL(k_discard_cols, dim3((unsigned)((m * l + 255) / 256)), dim3(256), 0, s,
                          w.Y, m, li, l, tsqr_root(w.pY), wp, nullptr, grank);
   }
-  if (!gram && o.ortho != TSSVD_ORTHO_ONCE) {
+  if (!gram && !cqr_last && o.ortho != TSSVD_ORTHO_ONCE) {
     // last step orthonormalized twice (Algorithm 2 form), gated like tssvd; with the discard
     // the second pass always runs (Algorithm 2) and applies the rule again
     TRY(gemm_atq_f64(w.Y, TSSVD_F64, l, m, l, w.Y, li, li, w.G, li, w.part, s));

@@ -144,10 +144,18 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const double* __restrict__ L, i
                                                  int64_t m, int64_t n, int K,
                                                  TC* __restrict__ C, int64_t ldc) {
   constexpr int TM = 2, TN = 4;
+  // tile L = (row block, column block), column block fastest; workgroup IDs are dealt to
+  // the 8 XCDs round-robin, so XCD x takes the contiguous tiles x*per ... and the column
+  // blocks of one row block share that XCD's L2 copy of their rows of L
+  const int64_t gx = (n + 127) / 128, total = gx * ((m + 63) / 64);
+  const int64_t per = (total + 7) / 8;
+  const int64_t tile = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (tile >= total) return;
+  const int64_t rowblk = tile / gx, colblk = tile - rowblk * gx;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
-  const int64_t rb = (int64_t)blockIdx.y * 64 + (wave & 1) * 32;
-  const int64_t cb = (int64_t)blockIdx.x * 128 + (wave >> 1) * 64;
+  const int64_t rb = rowblk * 64 + (wave & 1) * 32;
+  const int64_t cb = colblk * 128 + (wave >> 1) * 64;
   f64x4 acc[TM][TN];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
@@ -302,7 +310,8 @@ hipError_t zero_fill(double* p, int64_t count, hipStream_t s) {
 
 hipError_t gemm_nt(const double* L, int64_t ldl, const double* R, int64_t ldr, int64_t m,
                    int64_t n, int K, void* C, int c_dtype, int64_t ldc, hipStream_t s) {
-  dim3 grid((unsigned)((n + 127) / 128), (unsigned)((m + 63) / 64));
+  const int64_t total = ((n + 127) / 128) * ((m + 63) / 64);
+  dim3 grid((unsigned)(8 * ((total + 7) / 8)));
   const bool vec = (reinterpret_cast<uintptr_t>(L) & 15) == 0 &&
                    (reinterpret_cast<uintptr_t>(R) & 15) == 0 && ldl % 2 == 0 && ldr % 2 == 0 &&
                    K % 4 == 0;
