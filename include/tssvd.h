@@ -228,6 +228,10 @@ int tssvd_noalloc(const void* A, int32_t a_dtype, int64_t m, int64_t n, int64_t 
  * 5 is the TSQR's Householder Q with the columns whose |R_jj| < wp |R_11| dropped (set to
  * zero), and the last basis is orthonormalized twice with the rule applied after each pass.
  * Triplets past the kept rank come back as zero columns with S = 0; info->rank is the rank.
+ * Otherwise (wp = 0, ortho AUTO or TWICE) the last basis takes Algorithm 2's two
+ * orthonormalizations as CholeskyQR, each with a device gate to the Householder TSQR
+ * (non-positive pivot or ||R||_F ||R^-1||_F > 1e4), the second decided by opts->ortho and
+ * reorth_tol as in tssvd; with ORTHO_ONCE it is the TSQR's Householder Q.
  * With TSSVD_FLAG_GRAM the call runs Algorithm 8 instead (see the flag).
  * ------------------------------------------------------------------------------------- */
 int lowrank_svd_workspace_bytes(int64_t m, int64_t n, int64_t k, int64_t l, int64_t q,
