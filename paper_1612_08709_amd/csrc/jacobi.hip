@@ -127,8 +127,7 @@ __global__ __launch_bounds__(NT) void k_jacobi(
           const int il = lane16 + 16 * (NPL - 1);
           const bool lv = il < n;  // the last entry is a row of the matrix
           const int ilc = lv ? il : n - 1;
-          // the pair's entries of M and V stay in registers from the dot products to the
-          // rotation; the V loads are in flight during the reductions
+          // the pair's entries of M stay in registers from the dot products to the rotation
           double xr[NPL], yr[NPL], vxr[NPL], vyr[NPL];
 #pragma unroll
           for (int k = 0; k < NPL; ++k) {
@@ -136,13 +135,6 @@ __global__ __launch_bounds__(NT) void k_jacobi(
             xr[k] = mp[i];
             yr[k] = mq[i];
           }
-#pragma unroll
-          for (int k = 0; k < NPL; ++k) {
-            const int i = (k == NPL - 1) ? ilc : lane16 + 16 * k;
-            vxr[k] = vp[i];
-            vyr[k] = vq[i];
-          }
-          asm volatile("" ::: "memory");  // issue the V loads here, not after the reductions
           if (!lv) {
             xr[NPL - 1] = 0.0;
             yr[NPL - 1] = 0.0;
@@ -159,6 +151,16 @@ __global__ __launch_bounds__(NT) void k_jacobi(
           // tan(theta) = 2 ga sign(d) / (|d| + sqrt(d^2 + 4 ga^2)), d = be - al: the smaller
           // root of t^2 + 2 zeta t - 1 = 0 with zeta = d / (2 ga), one division.
           if (ga != 0.0 && ga * ga > tol2 * al * be) {
+            // V is read only for a pair that rotates (in the last sweeps most pairs do not,
+            // and the rounds are bound by the local data share's traffic), in flight while
+            // the rotation is computed
+#pragma unroll
+            for (int k = 0; k < NPL; ++k) {
+              const int i = (k == NPL - 1) ? ilc : lane16 + 16 * k;
+              vxr[k] = vp[i];
+              vyr[k] = vq[i];
+            }
+            asm volatile("" ::: "memory");
             const double d = be - al;
             const double g2 = 2.0 * ga;
             const double tt = (d >= 0.0 ? g2 : -g2) / (fabs(d) + sqrt(fma(d, d, g2 * g2)));
