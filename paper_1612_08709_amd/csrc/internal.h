@@ -71,7 +71,8 @@ hipError_t tsqr_apply(const TsqrPlan& p, const double* S, int k, double* out, in
 
 // Blocked leaf kernels (csrc/tsqr_wy.hip), used by tsqr_factor / tsqr_apply when ntw > 0.
 hipError_t wy_factor(const TsqrPlan& p, const void* A, int a_dtype, int64_t lda, hipStream_t s);
-hipError_t wy_apply(const TsqrPlan& p, int k, double* out, int64_t ldo, hipStream_t s);
+hipError_t wy_apply(const TsqrPlan& p, const double* S0, int k, double* out, int64_t ldo,
+                    hipStream_t s);
 // elements of storage per block: V, the ntw panel factors T_p and the Z_cp pairs
 size_t wy_block_elems(int ntw);
 

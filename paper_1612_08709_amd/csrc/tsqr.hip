@@ -458,21 +458,20 @@ static hipError_t apply_impl(const TsqrPlan& p, const double* S, int k, double* 
                              int64_t ldo, hipStream_t s, bool prof) {
   const int n = p.n;
   const int L = (int)p.cnt.size();
-  hipError_t e = hipMemcpyAsync(p.Slev[L - 1], S, (size_t)n * k * sizeof(double),
-                                hipMemcpyDeviceToDevice, s);
-  if (e != hipSuccess) return e;
+  // the root's seed is S itself (n x k, stride k, the layout of every level's seeds)
+  auto seed = [&](int lev) -> const double* { return lev == L - 1 ? S : p.Slev[lev]; };
   const size_t lds = (size_t)n * k * sizeof(double);
   for (int l = L - 2; l >= 0; --l)
     hipLaunchKernelGGL((k_tree_apply<NC, TNR>), dim3(p.cnt[l + 1]), dim3(256), lds, s,
-                       p.Slev[l + 1], p.cnt[l], n, k, p.G, p.Vtree[l], p.tautree[l],
+                       seed(l + 1), p.cnt[l], n, k, p.G, p.Vtree[l], p.tautree[l],
                        p.Slev[l], p.gate);
   if (prof) prof_begin(TSSVD_PROF_LEAF_APPLY, s);
   if (p.ntw) {
-    e = wy_apply(p, k, out, ldo, s);
+    const hipError_t e = wy_apply(p, seed(0), k, out, ldo, s);
     if (e != hipSuccess) return e;
   } else {
     hipLaunchKernelGGL((k_leaf_apply<NC, NR>), dim3(p.W), dim3(256), lds, s, p.Vleaf,
-                       p.tauleaf, p.Slev[0], n, k, p.bpw, p.nblocks, p.m, out, ldo, p.gate);
+                       p.tauleaf, seed(0), n, k, p.bpw, p.nblocks, p.m, out, ldo, p.gate);
   }
   if (prof) prof_end(TSSVD_PROF_LEAF_APPLY, s);
   return hipGetLastError();

@@ -713,8 +713,8 @@ static hipError_t wy_factor_launch(const TsqrPlan& p, const void* A, int a_dtype
 }
 
 template <typename CT, int NT, typename OT>
-static hipError_t wy_apply_launch(const TsqrPlan& p, int k, OT* out, int64_t ldo,
-                                  hipStream_t s) {
+static hipError_t wy_apply_launch(const TsqrPlan& p, const double* S0, int k, OT* out,
+                                  int64_t ldo, hipStream_t s) {
   constexpr bool ZS = wa_zs<CT, NT>();
   const size_t lds = wa_lds<CT, NT>(ZS);
   static bool attr = false;
@@ -725,7 +725,7 @@ static hipError_t wy_apply_launch(const TsqrPlan& p, int k, OT* out, int64_t ldo
     attr = true;
   }
   hipLaunchKernelGGL((k_wy_apply<CT, NT, OT, ZS>), dim3(p.W), dim3(64 * WA_WAVES), lds, s,
-                     (const CT*)p.Vwy, (const CT*)p.Twy, (const CT*)p.Zwy, p.Slev[0], p.n, k,
+                     (const CT*)p.Vwy, (const CT*)p.Twy, (const CT*)p.Zwy, S0, p.n, k,
                      p.bpw, p.nblocks, p.m, out, ldo, p.gate);
   return hipGetLastError();
 }
@@ -745,15 +745,16 @@ static hipError_t wy_factor_ct(const TsqrPlan& p, const void* A, int a_dtype, in
 }
 
 template <typename CT, typename OT>
-static hipError_t wy_apply_ct(const TsqrPlan& p, int k, OT* out, int64_t ldo, hipStream_t s) {
+static hipError_t wy_apply_ct(const TsqrPlan& p, const double* S0, int k, OT* out, int64_t ldo,
+                              hipStream_t s) {
   if (k < 1 || k > 16 * p.ntw) return hipErrorInvalidValue;  // W holds ntw x ntw tiles
   switch (p.ntw) {
-    case 3: return wy_apply_launch<CT, 3>(p, k, out, ldo, s);
-    case 4: return wy_apply_launch<CT, 4>(p, k, out, ldo, s);
-    case 5: return wy_apply_launch<CT, 5>(p, k, out, ldo, s);
-    case 6: return wy_apply_launch<CT, 6>(p, k, out, ldo, s);
-    case 7: return wy_apply_launch<CT, 7>(p, k, out, ldo, s);
-    case 8: return wy_apply_launch<CT, 8>(p, k, out, ldo, s);
+    case 3: return wy_apply_launch<CT, 3>(p, S0, k, out, ldo, s);
+    case 4: return wy_apply_launch<CT, 4>(p, S0, k, out, ldo, s);
+    case 5: return wy_apply_launch<CT, 5>(p, S0, k, out, ldo, s);
+    case 6: return wy_apply_launch<CT, 6>(p, S0, k, out, ldo, s);
+    case 7: return wy_apply_launch<CT, 7>(p, S0, k, out, ldo, s);
+    case 8: return wy_apply_launch<CT, 8>(p, S0, k, out, ldo, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -763,8 +764,10 @@ hipError_t wy_factor(const TsqrPlan& p, const void* A, int a_dtype, int64_t lda,
                  : wy_factor_ct<double>(p, A, a_dtype, lda, s);
 }
 
-hipError_t wy_apply(const TsqrPlan& p, int k, double* out, int64_t ldo, hipStream_t s) {
-  return p.wyf32 ? wy_apply_ct<float>(p, k, out, ldo, s) : wy_apply_ct<double>(p, k, out, ldo, s);
+hipError_t wy_apply(const TsqrPlan& p, const double* S0, int k, double* out, int64_t ldo,
+                    hipStream_t s) {
+  return p.wyf32 ? wy_apply_ct<float>(p, S0, k, out, ldo, s)
+                 : wy_apply_ct<double>(p, S0, k, out, ldo, s);
 }
 
 }  // namespace tsv
