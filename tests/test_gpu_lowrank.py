@@ -117,3 +117,21 @@ def test_workload2_full_size():
     e = checks.spectral_residual(Ah, U, S, V, iters=20)
     er = checks.spectral_residual(Ah, Ur, Sr, Vr, iters=20)
     assert abs(e - er) <= 1e-10
+
+
+@pytest.mark.parametrize("mode", ["once", "auto", "twice"])
+@pytest.mark.parametrize("m,n,k,l,q", [(5000, 300, 20, 40, 2), (3000, 200, 10, 12, 0)])
+def test_last_basis_orthonormalization_modes(mode, m, n, k, l, q):
+    """The last basis of Algorithm 5: ONCE takes the TSQR's Householder Q; AUTO and TWICE take
+    Algorithm 2's two orthonormalizations as CholeskyQR passes (the second one gated in
+    AUTO, always run in TWICE).  Every mode matches the oracle and returns U and V
+    orthonormal to 1e-13."""
+    flush_print("case lowrank last basis", mode, m, n, k, l, q)
+    ortho = {"once": T.ORTHO_ONCE, "auto": T.ORTHO_AUTO, "twice": T.ORTHO_TWICE}[mode]
+    A = sm.planted(m, n, 1.0 / np.arange(1, min(m, n) + 1), workload=70 + l)
+    Om = sm.sketch(n, l, 70 + l)
+    U, S, V, info = _compare(A, Om, k, q, ortho=ortho)
+    if mode == "twice":
+        assert info["reorth"] == 1
+    if mode == "once":
+        assert info["reorth"] == 0
