@@ -335,8 +335,9 @@ __global__ __launch_bounds__(RINV_THREADS) void k_rinv_gate(const double* __rest
 
 // The same two steps for l <= LM <= 64 in one wave, with no barrier: lane j owns column j.
 // Cholesky (right-looking): at step k the pivot G_kk and the row R_k. = G_k. / sqrt(G_kk)
-// come from lane k and from each lane, and G_ij -= R_ki R_kj updates lane j's column, the
-// scalar R_ki read from lane i.  A lane keeps only the entries i <= j of its column
+// come from lane k and from each lane, and G_ij -= R_ki R_kj updates lane j's column, R_ki
+// a broadcast read of row k, which each step writes to LDS.  A lane keeps only the entries
+// i <= j of its column
 // meaningful; the rest take junk that is never read.  R goes to LDS transposed, and
 // T = R^-1 follows by the column sweep of back substitution on the identity (lane j solves
 // R t = e_j: t_p = b_p / R_pp, then b_i -= R_ip t_p for i < p), each R_ip a broadcast LDS
@@ -355,10 +356,19 @@ __global__ __launch_bounds__(64) void k_chol_rinv_gate(const double* __restrict_
                                                        int* __restrict__ use_q,
                                                        int* __restrict__ chol_bad) {
   __shared__ double Rt[LM * LM];  // Rt[p * LM + i] = R_ip
+  __shared__ double Rrow[LM];      // row k of R during step k
   const int j = threadIdx.x;
   double g[LM];
+  // unconditional loads from clamped addresses, all issued before any is used (the empty
+  // asm statements take the values where they stand, so no load is sunk into the lane
+  // condition below, where it would be waited for at once), then the selection
+  const int jc = j < l ? j : l - 1;
 #pragma unroll
-  for (int i = 0; i < LM; ++i) g[i] = (j < l && i <= j) ? G[i * l + j] : 0.0;
+  for (int i = 0; i < LM; ++i) g[i] = G[(i < l ? i : l - 1) * l + jc];
+#pragma unroll
+  for (int i = 0; i < LM; ++i) asm volatile("" : "+v"(g[i]));
+#pragma unroll
+  for (int i = 0; i < LM; ++i) g[i] = (j < l && i <= j) ? g[i] : 0.0;
   int fail = 0;
 #pragma unroll
   for (int k = 0; k < LM; ++k) {
@@ -368,8 +378,12 @@ __global__ __launch_bounds__(64) void k_chol_rinv_gate(const double* __restrict_
         fail = 1;
       } else {
         g[k] *= 1.0 / sqrt(piv);  // lane j >= k: R_kj
+        // row k of R through LDS: one write, then broadcast reads (no lane-to-scalar moves)
+        Rrow[j] = g[k];
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt 0: the row is written
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int i = k + 1; i < LM; ++i) g[i] = fma(-lane_bcast(g[k], i), g[k], g[i]);
+        for (int i = k + 1; i < LM; ++i) g[i] = fma(-Rrow[i], g[k], g[i]);
       }
     }
   }
@@ -382,12 +396,18 @@ __global__ __launch_bounds__(64) void k_chol_rinv_gate(const double* __restrict_
   }
   __builtin_amdgcn_s_waitcnt(0xc07f);  // the wave's LDS writes are done (lgkmcnt 0)
   __builtin_amdgcn_wave_barrier();
+  // b's identity start is formed only now (from an opaque zero taken after the writes of R),
+  // so it does not hold registers during the factorization
+  int zero = 0;
+  asm volatile("" : "+v"(zero));
   double b[LM];
 #pragma unroll
-  for (int i = 0; i < LM; ++i) b[i] = (i == j) ? 1.0 : 0.0;
+  for (int i = 0; i < LM; ++i) b[i] = (i == j + zero) ? 1.0 : 0.0;
   if (!fail) {
 #pragma unroll
     for (int p = LM - 1; p >= 0; --p) {
+      // keeps each step's LDS reads in that step (hoisted ahead, they had been spilled)
+      asm volatile("" ::: "memory");
       if (p < l) {
         const double t = b[p] / Rt[p * LM + p];
         b[p] = t;
